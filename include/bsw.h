@@ -1,0 +1,192 @@
+/*
+ * bsw.h -- C ABI of the MI355X (gfx950) library for the regularised-Bingham
+ * shallow-water discontinuous Galerkin method of Fernandez, Lopez-Ordonez and
+ * Gonzalez-Andrade (arXiv 2301.11238).
+ *
+ * The library evaluates the DG spatial operator of the paper's backward-Euler
+ * step (Sec. 5.1, Eq. WeakForm7), its element-block Jacobian (Appendix A,
+ * Eq. Newton) and the stage update, and drives whole solves.  All arrays named
+ * `void*` below are DEVICE pointers owned by the caller (for example
+ * torch.Tensor.data_ptr()); their element type is the discretisation's
+ * precision (double for BSW_FP64, float for BSW_FP32).  `double*` arguments
+ * named *_out or host_* are HOST pointers.  Handles are owned by the library
+ * and released by the matching *_destroy call.
+ *
+ * State layout ("SoA", elements fastest): W[f][i][e] with f the field, i the
+ * basis function, e the element.  Fields: 1-D (h, u, E11); 2-D
+ * (h, u1, u2, E11, E21, E12, E22) with E_ab = d u_b / d x_a, the velocity
+ * gradient of Sec. 3 (Eq. gradientVel).  Modal coefficients in the orthonormal
+ * basis: normalised Legendre on [-1, 1] (Sec. 5) and the orthonormal Dubiner
+ * basis on the unit triangle, modes ordered by total degree then by the
+ * second index.  b_old and the first 1+d fields of R use the same layout.
+ *
+ * Every call returns an int status: BSW_OK (0), a negative error, or a
+ * positive warning.  Nothing throws across this boundary.  bsw_last_error()
+ * returns the context's last message.  Device work is enqueued on the
+ * context's HIP stream and is asynchronous unless a host output is requested
+ * (norms, diagnostics, solve statistics), in which case the call synchronises
+ * that stream.
+ */
+#ifndef BSW_H
+#define BSW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BSW_OK = 0,
+  BSW_E_ARG = -1,         /* invalid argument (sizes, null pointers, unsupported order) */
+  BSW_E_OOM = -2,         /* device allocation failed */
+  BSW_E_HIP = -3,         /* a HIP runtime call failed */
+  BSW_E_STATE = -4,       /* call out of order (e.g. Jacobian apply before linearize) */
+  BSW_E_MESH = -5,        /* degenerate or non-manifold mesh */
+  BSW_W_NOT_CONVERGED = 1 /* warning: some Newton step hit its iteration cap */
+};
+
+enum { BSW_FP64 = 0, BSW_FP32 = 1 };
+enum { BSW_REG1 = 1, BSW_REG2 = 2, BSW_REG3 = 3 };
+enum { BSW_BC_WALL = 1, BSW_BC_NEUMANN = 2, BSW_BC_DIRICHLET = 3 };
+enum {
+  BSW_IC_CONST = 0, BSW_IC_STEP_X = 1, BSW_IC_MOUND = 2, BSW_IC_DISK = 3,
+  BSW_IC_SINE_U = 4, BSW_IC_LINEAR_X = 5, BSW_IC_SHEAR_Y = 6, BSW_IC_VORTEX = 7
+};
+
+typedef struct bsw_ctx_s* bsw_ctx;
+typedef struct bsw_mesh_s* bsw_mesh;
+typedef struct bsw_disc_s* bsw_disc;
+
+/* Physical and regularisation parameters (Sec. 3: g, rho, alpha; Sec. 4: eta,
+ * sigma0, gamma, beta and the regularisation k = reg in {1, 2, 3}).
+ * bc applies to every boundary face: wall (mirror state: h+ = h-, u+ = R u-,
+ * E+ = R E- R with R = I - 2 n n^T), homogeneous Neumann (V+ = V-, E+ = E-,
+ * Sec. 5.2) or Dirichlet (exterior state = dirichlet[0..n_f-1], Sec. 5.2).
+ * Regularisations 1 and 2 need sigma0 = 0 or sigma0 >= 1 / (2 beta). */
+typedef struct {
+  double g, rho, alpha, eta, sigma0, gamma, beta;
+  int32_t reg;
+  int32_t bc;
+  double dirichlet[7];
+} bsw_params;
+
+/* Analytic initial condition, L2-projected with the element rule; E = 0.
+ * kinds: CONST h=a,u=(b,c); STEP_X h = x<x0 ? a : b; MOUND h = a+b exp(-|x-x0,y0|^2/d);
+ * DISK h = |x-(x0,y0)|<r ? a : b; SINE_U h=a,u1=b sin(pi x/L); LINEAR_X h=a+b x;
+ * SHEAR_Y h=a,u1=b cos(pi y/L); VORTEX h=a, u=b(sin(pi x/L)cos(pi y/L), -cos(pi x/L)sin(pi y/L)). */
+typedef struct {
+  int32_t kind;
+  double a, b, c, d, x0, y0, r, L;
+} bsw_ic;
+
+/* Whole-solve controls (Sec. 5.1 and Sec. 6: at most max_newton = 10 Newton
+ * iterations per step).  dt > 0 fixes the step; otherwise
+ * dt = cfl * h_min / max(|u| + sqrt(g h)) over the initial state's volume
+ * points, and the last step is clipped to land on t_end. */
+typedef struct {
+  int32_t max_newton;      /* Newton iterations per time step */
+  int32_t gmres_m;         /* GMRES restart length (<= 64) */
+  int32_t gmres_max_iters; /* total GMRES iterations per Newton system */
+  double newton_tol;       /* stop when ||dW||_inf <= newton_tol (1 + ||W||_inf) */
+  double gmres_rtol;       /* relative residual of each Newton system */
+  double cfl, t_end, dt;
+  int32_t max_steps;       /* < 0: all steps */
+} bsw_solve_opts;
+
+typedef struct {
+  int32_t steps, newton_total, gmres_total, newton_max, capped, status;
+  double dt, mass0, mass_end, max_mass_drift, active_pct, t_end, seconds;
+  double operator_applies, jacobian_applies; /* counts of whole-mesh applies */
+} bsw_solve_stats;
+
+/* ---------------------------------------------------------------- context */
+/* Binds a device and a HIP stream (NULL: the null stream; the caller may pass
+ * torch's current stream).  The stream must outlive the context. */
+int bsw_ctx_create(int device, void* hip_stream, bsw_ctx* out);
+int bsw_ctx_destroy(bsw_ctx ctx);
+const char* bsw_last_error(bsw_ctx ctx);
+
+/* ---------------------------------------------------------------- mesh (Sec. 5: Omega^h = U Omega_e^h) */
+/* Host inputs: xy[n_vert * dim] vertex coordinates; el2vert[n_el * (dim+1)]
+ * counter-clockwise triangles (2-D) or increasing segments (1-D).  The library
+ * builds face->neighbour maps, outward normals, face lengths and the affine
+ * metrics on the host and copies them to the device; the host arrays may be
+ * freed on return.  Returns BSW_E_MESH for non-positive Jacobians or faces
+ * shared by more than two elements. */
+int bsw_mesh_upload(bsw_ctx ctx, int dim, int64_t n_vert, const double* xy, int64_t n_el,
+                    const int32_t* el2vert, bsw_mesh* out);
+int bsw_mesh_destroy(bsw_mesh mesh);
+
+/* ---------------------------------------------------------------- discretisation */
+/* Order P (1-D: 0..4; triangles: 1..3 with 3/7/12-point volume rules and P+1
+ * Gauss points per edge) and precision (BSW_FP64 or BSW_FP32).  Builds the
+ * reference tables (basis and gradients at the volume points, basis at the
+ * face points, weights) in FP64 on the host and stages them in constant
+ * memory.  The mesh must outlive the discretisation. */
+int bsw_disc_create(bsw_mesh mesh, int P, int precision, bsw_disc* out);
+int bsw_disc_destroy(bsw_disc disc);
+/* info[8] = {dim, P, n_p, n_q, n_fq, n_faces_per_element, n_f, n_el} */
+int bsw_disc_info(bsw_disc disc, int64_t* info);
+/* n_f * n_p * n_el: the number of reals in W */
+int64_t bsw_state_len(bsw_disc disc);
+
+/* L2 projection of an analytic initial condition into W (device). */
+int bsw_project_ic(bsw_disc disc, const bsw_ic* ic, void* W);
+
+/* ---------------------------------------------------------------- the operator */
+/* b_old[f][i][e] = (1/dt) <phi_i, U_f(W_old)>_e for f < 1+d: the old-time part
+ * of the first term of Eq. WeakForm7 (U = (h, h u), Eq. Uterm). */
+int bsw_step_begin(bsw_disc disc, const bsw_params* prm, double dt, const void* W_old,
+                   void* b_old);
+
+/* R = the element residuals of Eq. WeakForm7 at W given b_old: volume fluxes
+ * F (Eq. Fterm), the regularised Bingham stress term Q (Eq. Qterm, Sec. 4),
+ * the source S (Eq. Sterm, flat bed), the auxiliary equation for E (Eq. Gterm),
+ * HLL face fluxes for F (Eq. HLLSolver) and central ones for Q and G (Sec. 5).
+ * Layout of R as W.  W, b_old and R must not alias. */
+int bsw_operator_apply(bsw_disc disc, const bsw_params* prm, double dt, const void* W,
+                       const void* b_old, void* R);
+
+/* ---------------------------------------------------------------- element-block Jacobian (Appendix A) */
+/* Records W (device pointer, kept by reference: the caller must not change or
+ * free it until the next linearize), the parameters and dt; assembles the
+ * diagonal blocks dR_e/dW_e of Eq. Newton and LU-factors them (partial
+ * pivoting) for the block-Jacobi preconditioner. */
+int bsw_jacobian_linearize(bsw_disc disc, const bsw_params* prm, double dt, const void* W);
+/* y = (dR/dW)(W) x, the exact directional derivative including the HLL wave
+ * speeds and the face coupling to neighbours (matrix-free).  BSW_E_STATE
+ * before the first linearize. */
+int bsw_jacobian_apply(bsw_disc disc, const void* x, void* y);
+/* y = blockdiag(dR_e/dW_e)^{-1} x using the factors of the last linearize. */
+int bsw_precond_apply(bsw_disc disc, const void* x, void* y);
+/* Writes the unfactored diagonal blocks of the last linearize to blocks
+ * (device, [n_el][bs][bs] row-major, bs = n_f n_p, row/column index f*n_p+i). */
+int bsw_jacobian_blocks(bsw_disc disc, void* blocks);
+
+/* ---------------------------------------------------------------- stage update and reductions */
+/* W += alpha dW (Eq. Newton update).  norms_out (host, may be NULL) receives
+ * FP64 {max|alpha dW|, max|W|, mass, active%} after the update, where
+ * mass = sum_e sum_q w_q h(x_q) and active% = 100/|Omega| sum w_q H(s - sigma0/gamma)
+ * (Sec. 6) with s the shear rate of the 2-D reading (|E| in 1-D). */
+int bsw_stage_update(bsw_disc disc, const bsw_params* prm, void* W, const void* dW,
+                     double alpha, double* norms_out);
+/* out4 (host) = {mass, active%, max(|u| + sqrt(g h)), min h} over volume points. */
+int bsw_diagnostics(bsw_disc disc, const bsw_params* prm, const void* W, double* out4);
+/* *out (host) = sqrt(sum x^2) accumulated in FP64. */
+int bsw_norm2(bsw_disc disc, const void* x, double* out);
+
+/* ---------------------------------------------------------------- whole solve */
+/* Backward-Euler time loop from the state in W (device, updated in place) to
+ * opts->t_end: per step b_old, then Newton (residual, linearize, block-Jacobi
+ * GMRES for Eq. Newton, backtracking on ||R||, update) until
+ * ||dW||_inf <= newton_tol (1 + ||W||_inf) or max_newton iterations.
+ * Returns BSW_W_NOT_CONVERGED if any step hit the cap. */
+int bsw_solve(bsw_disc disc, const bsw_params* prm, const bsw_solve_opts* opts, void* W,
+              bsw_solve_stats* stats_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSW_H */

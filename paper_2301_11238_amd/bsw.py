@@ -1,0 +1,293 @@
+"""Thin ctypes binding of the C ABI in include/bsw.h.
+
+Every function here marshals arguments and calls the same-named entry point of
+libbsw.so; all arithmetic of the method runs in the library's HIP kernels.
+Device arrays are torch tensors (memory and streams only).  The library must
+be built (paper_2301_11238_amd/build.py); importing fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsw.so")
+
+BSW_OK, BSW_W_NOT_CONVERGED = 0, 1
+BSW_FP64, BSW_FP32 = 0, 1
+
+
+class BswError(RuntimeError):
+    pass
+
+
+class Params(C.Structure):
+    _fields_ = [("g", C.c_double), ("rho", C.c_double), ("alpha", C.c_double), ("eta", C.c_double),
+                ("sigma0", C.c_double), ("gamma", C.c_double), ("beta", C.c_double),
+                ("reg", C.c_int32), ("bc", C.c_int32), ("dirichlet", C.c_double * 7)]
+
+
+class IC(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
+                ("d", C.c_double), ("x0", C.c_double), ("y0", C.c_double), ("r", C.c_double),
+                ("L", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("max_newton", C.c_int32), ("gmres_m", C.c_int32), ("gmres_max_iters", C.c_int32),
+                ("newton_tol", C.c_double), ("gmres_rtol", C.c_double), ("cfl", C.c_double),
+                ("t_end", C.c_double), ("dt", C.c_double), ("max_steps", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("newton_total", C.c_int32), ("gmres_total", C.c_int32),
+                ("newton_max", C.c_int32), ("capped", C.c_int32), ("status", C.c_int32),
+                ("dt", C.c_double), ("mass0", C.c_double), ("mass_end", C.c_double),
+                ("max_mass_drift", C.c_double), ("active_pct", C.c_double), ("t_end", C.c_double),
+                ("seconds", C.c_double), ("operator_applies", C.c_double),
+                ("jacobian_applies", C.c_double)]
+
+
+# name -> (restype, argtypes); the exported symbols declared in include/bsw.h
+_VP, _DP, _I64P = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+SIGNATURES = {
+    "bsw_ctx_create": (C.c_int, [C.c_int, _VP, C.POINTER(_VP)]),
+    "bsw_ctx_destroy": (C.c_int, [_VP]),
+    "bsw_last_error": (C.c_char_p, [_VP]),
+    "bsw_mesh_upload": (C.c_int, [_VP, C.c_int, C.c_int64, _DP, C.c_int64, C.POINTER(C.c_int32), C.POINTER(_VP)]),
+    "bsw_mesh_destroy": (C.c_int, [_VP]),
+    "bsw_disc_create": (C.c_int, [_VP, C.c_int, C.c_int, C.POINTER(_VP)]),
+    "bsw_disc_destroy": (C.c_int, [_VP]),
+    "bsw_disc_info": (C.c_int, [_VP, _I64P]),
+    "bsw_state_len": (C.c_int64, [_VP]),
+    "bsw_project_ic": (C.c_int, [_VP, C.POINTER(IC), _VP]),
+    "bsw_step_begin": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP, _VP]),
+    "bsw_operator_apply": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP, _VP, _VP]),
+    "bsw_jacobian_linearize": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP]),
+    "bsw_jacobian_apply": (C.c_int, [_VP, _VP, _VP]),
+    "bsw_precond_apply": (C.c_int, [_VP, _VP, _VP]),
+    "bsw_jacobian_blocks": (C.c_int, [_VP, _VP]),
+    "bsw_stage_update": (C.c_int, [_VP, C.POINTER(Params), _VP, _VP, C.c_double, _DP]),
+    "bsw_diagnostics": (C.c_int, [_VP, C.POINTER(Params), _VP, _DP]),
+    "bsw_norm2": (C.c_int, [_VP, _VP, _DP]),
+    "bsw_solve": (C.c_int, [_VP, C.POINTER(Params), C.POINTER(SolveOpts), _VP, C.POINTER(SolveStats)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libbsw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise BswError(f"{LIB_PATH} is missing: build it with paper_2301_11238_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def make_params(p, bc: int = 1, dirichlet=None) -> Params:
+    q = Params()
+    for k in ("g", "rho", "alpha", "eta", "sigma0", "gamma", "beta"):
+        setattr(q, k, float(getattr(p, k)))
+    q.reg = int(p.reg)
+    q.bc = int(bc)
+    if dirichlet is not None:
+        for i, v in enumerate(dirichlet):
+            q.dirichlet[i] = float(v)
+    return q
+
+
+def make_ic(ic) -> IC:
+    c = IC()
+    c.kind = int(ic.kind)
+    for k in ("a", "b", "c", "d", "x0", "y0", "r", "L"):
+        setattr(c, k, float(getattr(ic, k)))
+    return c
+
+
+@dataclass
+class Options:
+    max_newton: int = 10
+    gmres_m: int = 30
+    gmres_max_iters: int = 1200
+    newton_tol: float = 1e-12
+    gmres_rtol: float = 1e-12
+    cfl: float = 0.2
+    t_end: float = 1.0
+    dt: float = 0.0
+    max_steps: int = -1
+
+    def c(self) -> SolveOpts:
+        o = SolveOpts()
+        for k, _ in SolveOpts._fields_:
+            setattr(o, k, getattr(self, k))
+        return o
+
+
+class Context:
+    """bsw_ctx on one device, bound to a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = C.c_void_p()
+        self._check(lib().bsw_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)), None)
+        self.h = h
+
+    def _check(self, rc, h=None):
+        if rc < 0:
+            msg = lib().bsw_last_error(h if h is not None else getattr(self, "h", None))
+            raise BswError(f"bsw error {rc}: {msg.decode() if msg else ''}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bsw_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    def __init__(self, ctx: Context, dim: int, xy, el2vert):
+        import numpy as np
+        self.ctx = ctx
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        e2v = np.ascontiguousarray(el2vert, dtype=np.int32)
+        h = C.c_void_p()
+        ctx._check(lib().bsw_mesh_upload(ctx.h, dim, xy.shape[0], xy.ctypes.data_as(_DP), e2v.shape[0],
+                                         e2v.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)), ctx.h)
+        self.h = h
+        self.dim = dim
+        self.n_el = e2v.shape[0]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bsw_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Disc:
+    """bsw_disc: one (mesh, order, precision); methods mirror the C ABI."""
+
+    def __init__(self, mesh: Mesh, P: int, precision: int = BSW_FP64):
+        import torch
+        self.mesh, self.ctx = mesh, mesh.ctx
+        h = C.c_void_p()
+        self.ctx._check(lib().bsw_disc_create(mesh.h, P, precision, C.byref(h)), self.ctx.h)
+        self.h = h
+        info = (C.c_int64 * 8)()
+        lib().bsw_disc_info(h, info)
+        self.dim, self.P, self.np, self.nq, self.nfq, self.nfc, self.nf, self.n_el = [int(v) for v in info]
+        self.precision = precision
+        self.dtype = torch.float64 if precision == BSW_FP64 else torch.float32
+        self.shape = (self.nf, self.np, self.n_el)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bsw_disc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ck(self, rc):
+        return self.ctx._check(rc, self.ctx.h)
+
+    def empty(self, nfields=None):
+        import torch
+        nf = self.nf if nfields is None else nfields
+        return torch.empty((nf, self.np, self.n_el), dtype=self.dtype, device=self.ctx.torch_device)
+
+    def zeros(self):
+        import torch
+        return torch.zeros(self.shape, dtype=self.dtype, device=self.ctx.torch_device)
+
+    def state_len(self) -> int:
+        return int(lib().bsw_state_len(self.h))
+
+    def project_ic(self, ic, W=None):
+        W = self.empty() if W is None else W
+        self._ck(lib().bsw_project_ic(self.h, C.byref(make_ic(ic)), _ptr(W)))
+        return W
+
+    def step_begin(self, params: Params, dt: float, W_old, b_old=None):
+        b_old = self.empty(1 + self.dim) if b_old is None else b_old
+        self._ck(lib().bsw_step_begin(self.h, C.byref(params), float(dt), _ptr(W_old), _ptr(b_old)))
+        return b_old
+
+    def operator_apply(self, params: Params, dt: float, W, b_old, R=None):
+        R = self.empty() if R is None else R
+        self._ck(lib().bsw_operator_apply(self.h, C.byref(params), float(dt), _ptr(W), _ptr(b_old), _ptr(R)))
+        return R
+
+    def jacobian_linearize(self, params: Params, dt: float, W):
+        self._lin_W = W  # the library keeps a reference to W's memory
+        self._ck(lib().bsw_jacobian_linearize(self.h, C.byref(params), float(dt), _ptr(W)))
+
+    def jacobian_apply(self, x, y=None):
+        y = self.empty() if y is None else y
+        self._ck(lib().bsw_jacobian_apply(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def precond_apply(self, x, y=None):
+        y = self.empty() if y is None else y
+        self._ck(lib().bsw_precond_apply(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def jacobian_blocks(self):
+        import torch
+        bs = self.nf * self.np
+        out = torch.empty((self.n_el, bs, bs), dtype=self.dtype, device=self.ctx.torch_device)
+        self._ck(lib().bsw_jacobian_blocks(self.h, _ptr(out)))
+        return out
+
+    def stage_update(self, params, W, dW, alpha: float = 1.0):
+        out = (C.c_double * 4)()
+        self._ck(lib().bsw_stage_update(self.h, C.byref(params) if params is not None else None, _ptr(W),
+                                        _ptr(dW), float(alpha), out))
+        return list(out)
+
+    def diagnostics(self, params, W):
+        out = (C.c_double * 4)()
+        self._ck(lib().bsw_diagnostics(self.h, C.byref(params), _ptr(W), out))
+        return dict(mass=out[0], active_pct=out[1], lambda_max=out[2], h_min=out[3])
+
+    def norm2(self, x) -> float:
+        out = C.c_double(0.0)
+        self._ck(lib().bsw_norm2(self.h, _ptr(x), C.byref(out)))
+        return out.value
+
+    def solve(self, params: Params, opts: Options, W):
+        st = SolveStats()
+        rc = lib().bsw_solve(self.h, C.byref(params), C.byref(opts.c()), _ptr(W), C.byref(st))
+        self._ck(rc)
+        return {k: getattr(st, k) for k, _ in SolveStats._fields_}

@@ -1,0 +1,1148 @@
+// Host side of the library: C ABI (include/bsw.h), mesh and discretisation
+// setup, kernel dispatch over (dimension, order, precision), deterministic
+// reductions, and the backward-Euler / Newton / block-Jacobi GMRES driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bsw.h"
+#include "bsw_kernels.hpp"
+#include "ref_element.hpp"
+
+namespace bsw {
+__constant__ __align__(16) unsigned char c_tables[kTabBytesTotal];
+}
+
+using namespace bsw;
+
+// ====================================================================== handles
+struct bsw_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool tables_staged[2][kNumCombos] = {};
+};
+
+template <class T>
+struct DevMesh {
+  T* dxi = nullptr;
+  T* detJ = nullptr;
+  T* nrm = nullptr;
+  T* hlen = nullptr;
+};
+
+struct bsw_mesh_s {
+  bsw_ctx ctx = nullptr;
+  int dim = 0, nfc = 0;
+  int64_t n_el = 0, n_vert = 0;
+  double hmin = 0.0, measure = 0.0;
+  int* nbr = nullptr;      // device [nfc][n_el]
+  double* vert = nullptr;  // device [(dim+1)*dim][n_el]
+  DevMesh<double> m64;
+  DevMesh<float> m32;
+  std::vector<double> h_dxi, h_detJ, h_nrm, h_hlen;  // host copies for the FP32 view
+};
+
+struct bsw_disc_s {
+  bsw_mesh mesh = nullptr;
+  int P = 0, precision = BSW_FP64;
+  RefElement ref;
+  int bs = 0;
+  size_t wsize = 0;  // bytes per real
+  // linearisation
+  const void* lin_W = nullptr;
+  bsw_params lin_prm{};
+  double lin_dt = 0.0;
+  void* blocks = nullptr;  // factored [bs][bs][n_el]
+  void* blocks_raw = nullptr;  // unfactored copy (kept for inspection)
+  int* perm = nullptr;
+  // reduction scratch
+  double* part = nullptr;
+  size_t part_len = 0;
+  double* red_out = nullptr;      // device [64]
+  double* red_host = nullptr;     // pinned [64]
+  // solver workspace
+  void* gm = nullptr;             // GMRES Krylov basis and vectors
+  size_t gm_bytes = 0;
+  double* hcoef = nullptr;        // device [65]
+};
+
+namespace {
+
+thread_local std::string g_err_no_ctx;
+
+inline void hfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int fail(bsw_ctx c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_err_no_ctx = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t _e = (call);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail((ctx), BSW_E_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+template <class T>
+int dev_alloc(bsw_ctx c, T** p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return fail(c, BSW_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return BSW_OK;
+}
+
+int combo_index(int dim, int P) {
+  for (int k = 0; k < kNumCombos; ++k)
+    if (kCombo[k][0] == dim && kCombo[k][1] == P) return k;
+  return -1;
+}
+
+// ---------------------------------------------------------------- dispatch
+template <class T, class F>
+int dispatchT(int dim, int P, F& f) {
+  if (dim == 1) {
+    switch (P) {
+      case 0: return f.template operator()<1, 0, T>();
+      case 1: return f.template operator()<1, 1, T>();
+      case 2: return f.template operator()<1, 2, T>();
+      case 3: return f.template operator()<1, 3, T>();
+      case 4: return f.template operator()<1, 4, T>();
+    }
+  } else {
+    switch (P) {
+      case 1: return f.template operator()<2, 1, T>();
+      case 2: return f.template operator()<2, 2, T>();
+      case 3: return f.template operator()<2, 3, T>();
+    }
+  }
+  return BSW_E_ARG;
+}
+
+template <class F>
+int dispatch(bsw_disc d, F&& f) {
+  if (d->precision == BSW_FP64) return dispatchT<double>(d->mesh->dim, d->P, f);
+  return dispatchT<float>(d->mesh->dim, d->P, f);
+}
+
+template <class T>
+MeshView<T> view(bsw_disc d) {
+  MeshView<T> v;
+  v.n_el = (int)d->mesh->n_el;
+  const DevMesh<T>* dm;
+  if constexpr (sizeof(T) == 8) dm = &d->mesh->m64; else dm = &d->mesh->m32;
+  v.dxi = dm->dxi; v.detJ = dm->detJ; v.nrm = dm->nrm; v.hlen = dm->hlen;
+  v.nbr = d->mesh->nbr;
+  v.vert = d->mesh->vert;
+  return v;
+}
+
+template <class T>
+DevParams<T> devparams(const bsw_params& p, double dt) {
+  DevParams<T> q;
+  q.g = (T)p.g;
+  q.gc = (T)(p.g * std::cos(p.alpha));
+  q.gs = (T)(p.g * std::sin(p.alpha));
+  q.rho_inv = (T)(1.0 / p.rho);
+  q.eta = (T)p.eta; q.s0 = (T)p.sigma0; q.gam = (T)p.gamma; q.bet = (T)p.beta;
+  q.inv_dt = dt > 0 ? (T)(1.0 / dt) : T(0);
+  q.reg = p.reg; q.bc = p.bc;
+  for (int k = 0; k < 7; ++k) q.dir[k] = (T)p.dirichlet[k];
+  return q;
+}
+
+int check_params(bsw_disc d, const bsw_params* p) {
+  bsw_ctx c = d->mesh->ctx;
+  if (!p) return fail(c, BSW_E_ARG, "params is null");
+  if (p->reg < 1 || p->reg > 3) return fail(c, BSW_E_ARG, "reg must be 1, 2 or 3");
+  if (p->bc < 1 || p->bc > 3) return fail(c, BSW_E_ARG, "bc must be 1 (wall), 2 (Neumann) or 3 (Dirichlet)");
+  if (!(p->g > 0) || !(p->rho > 0) || p->eta < 0 || p->sigma0 < 0 || !(p->gamma > 0) || !(p->beta > 0))
+    return fail(c, BSW_E_ARG, "need g, rho, gamma, beta > 0 and eta, sigma0 >= 0");
+  if (p->reg != 3 && p->sigma0 > 0 && p->sigma0 < 0.5 / p->beta)
+    return fail(c, BSW_E_ARG, "regularisations 1 and 2 need sigma0 >= 1/(2 beta)");
+  return BSW_OK;
+}
+
+inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+// ---------------------------------------------------------------- reductions
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double red_op(double a, double b, int op) {
+  return op == 0 ? a + b : (op == 1 ? fmax(a, b) : fmin(a, b));
+}
+
+// block-level reduction of NV values per thread into part[v * nblk + blockIdx.x]
+template <int NV>
+__device__ void block_reduce(double (&val)[NV], const int (&ops)[NV], double* part) {
+  __shared__ double sh[NV][kRedThreads];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = val[v];
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = red_op(sh[v][threadIdx.x], sh[v][threadIdx.x + s], ops[v]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) part[v * gridDim.x + blockIdx.x] = sh[v][0];
+}
+
+// final pass: out[v] = reduce(part[v][0..nblk)), one block per value, fixed order
+__global__ void __launch_bounds__(kRedThreads) k_reduce_final(const double* __restrict__ part, int nblk,
+                                                               const int* __restrict__ ops_unused, int op0,
+                                                               int op1, int op2, int op3, double* out) {
+  const int v = blockIdx.x;
+  const int op = v == 0 ? op0 : (v == 1 ? op1 : (v == 2 ? op2 : op3));
+  const double init = op == 0 ? 0.0 : (op == 1 ? -INFINITY : INFINITY);
+  double acc = init;
+  for (int i = threadIdx.x; i < nblk; i += kRedThreads) acc = red_op(acc, part[(size_t)v * nblk + i], op);
+  __shared__ double sh[kRedThreads];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = red_op(sh[threadIdx.x], sh[threadIdx.x + s], op);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = sh[0];
+}
+
+// dot products of w with k vectors V[j] (stride ld) -> part[j][blk]
+template <class T>
+__global__ void __launch_bounds__(kRedThreads) k_multidot(const T* __restrict__ V, size_t ld, const T* __restrict__ w,
+                                                           int64_t n, double* __restrict__ part) {
+  const int j = blockIdx.y;
+  const T* v = V + (size_t)j * ld;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
+    acc += (double)v[i] * (double)w[i];
+  __shared__ double sh[kRedThreads];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)j * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_sum_rows(const double* __restrict__ part, int nblk, double* out) {
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kRedThreads) acc += part[(size_t)j * nblk + i];
+  __shared__ double sh[kRedThreads];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = sh[0];
+}
+
+// w += sgn * sum_j h[j] V[j] (coefficients passed by value)
+struct Coef {
+  double h[65];
+};
+template <class T>
+__global__ void __launch_bounds__(256) k_multi_axpy(T* __restrict__ w, const T* __restrict__ V, size_t ld, int k,
+                                                     Coef h, double sgn, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) s += h.h[j] * (double)V[(size_t)j * ld + i];
+  w[i] = (T)((double)w[i] + sgn * s);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_scale_copy(const T* __restrict__ x, T* __restrict__ y, double s, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (T)((double)x[i] * s);
+}
+
+// y = a x + b z
+template <class T>
+__global__ void __launch_bounds__(256) k_axpby(T* __restrict__ y, double a, const T* __restrict__ x, double b,
+                                                const T* __restrict__ z, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (T)(a * (double)x[i] + b * (double)z[i]);
+}
+
+// W += alpha dW with max|alpha dW| and max|W| partials
+template <class T>
+__global__ void __launch_bounds__(kRedThreads) k_axpy_norms(T* __restrict__ W, const T* __restrict__ dW, double alpha,
+                                                             int64_t n, double* part) {
+  double v[2] = {0.0, 0.0};
+  const int ops[2] = {1, 1};
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
+    const double d = alpha * (double)dW[i];
+    const T wn = (T)((double)W[i] + d);
+    W[i] = wn;
+    v[0] = fmax(v[0], fabs(d));
+    v[1] = fmax(v[1], fabs((double)wn));
+  }
+  block_reduce<2>(v, ops, part);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kRedThreads) k_absmax(const T* __restrict__ x, int64_t n, double* part) {
+  double v[1] = {0.0};
+  const int ops[1] = {1};
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
+    v[0] = fmax(v[0], fabs((double)x[i]));
+  block_reduce<1>(v, ops, part);
+}
+
+// mass, active area, max(|u| + sqrt(g h)), min h over volume points (Sec. 6)
+template <int D, int P, class T>
+__global__ void __launch_bounds__(kRedThreads) k_diag(const T* __restrict__ W, MeshView<T> m, double g, double thr,
+                                                       double* part) {
+  using S = Shape<D, P>;
+  const Tab<D, P, T>& tb = tab<D, P, T>();
+  double v[4] = {0.0, 0.0, 0.0, INFINITY};
+  const int ops[4] = {0, 0, 1, 2};
+  const int n = m.n_el;
+  for (int e = blockIdx.x * kRedThreads + threadIdx.x; e < n; e += gridDim.x * kRedThreads) {
+    T w[S::NF][S::NP];
+    load_coeffs<D, P, T>(W, n, e, w);
+    const double detJ = (double)m.detJ[e];
+#pragma unroll
+    for (int q = 0; q < S::NQ; ++q) {
+      T X[S::NF];
+      interp<D, P, T>(tb.phi[q], w, X);
+      const double wq = (double)tb.qw[q] * detJ;
+      const double h = (double)X[0];
+      v[0] += wq * h;
+      double tr = 0.0, n2 = 0.0, um = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) tr += (double)X[1 + D + a * D + a];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          const double dab = 0.5 * ((double)X[1 + D + b * D + a] + (double)X[1 + D + a * D + b]);
+          n2 += dab * dab;
+        }
+      const double s = sqrt(0.5 * (n2 + tr * tr));
+      if (s - thr >= 0.0) v[1] += wq;
+#pragma unroll
+      for (int b = 0; b < D; ++b) um += (double)X[1 + b] * (double)X[1 + b];
+      v[2] = fmax(v[2], sqrt(um) + sqrt(g * fmax(h, 0.0)));
+      v[3] = fmin(v[3], h);
+    }
+  }
+  block_reduce<4>(v, ops, part);
+}
+
+// L2 projection of an analytic initial condition (E = 0)
+__device__ void ic_eval(const bsw_ic& ic, int dim, double x, double y, double& h, double& u, double& v) {
+  u = 0.0; v = 0.0;
+  const double pi = 3.14159265358979323846;
+  switch (ic.kind) {
+    case BSW_IC_CONST: h = ic.a; u = ic.b; v = ic.c; break;
+    case BSW_IC_STEP_X: h = x < ic.x0 ? ic.a : ic.b; break;
+    case BSW_IC_MOUND: {
+      const double r2 = (x - ic.x0) * (x - ic.x0) + (dim == 2 ? (y - ic.y0) * (y - ic.y0) : 0.0);
+      h = ic.a + ic.b * exp(-r2 / ic.d);
+    } break;
+    case BSW_IC_DISK: {
+      const double r2 = (x - ic.x0) * (x - ic.x0) + (dim == 2 ? (y - ic.y0) * (y - ic.y0) : 0.0);
+      h = r2 < ic.r * ic.r ? ic.a : ic.b;
+    } break;
+    case BSW_IC_SINE_U: h = ic.a; u = ic.b * sin(pi * x / ic.L); break;
+    case BSW_IC_LINEAR_X: h = ic.a + ic.b * x; break;
+    case BSW_IC_SHEAR_Y: h = ic.a; u = ic.b * cos(pi * y / ic.L); break;
+    case BSW_IC_VORTEX:
+      h = ic.a;
+      u = ic.b * sin(pi * x / ic.L) * cos(pi * y / ic.L);
+      v = -ic.b * cos(pi * x / ic.L) * sin(pi * y / ic.L);
+      break;
+    default: h = 1.0;
+  }
+}
+
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) k_project_ic(T* __restrict__ W, MeshView<T> m, bsw_ic ic,
+                                                     const double* __restrict__ qxi) {
+  using S = Shape<D, P>;
+  const Tab<D, P, T>& tb = tab<D, P, T>();
+  const int n = m.n_el;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double acc[1 + D][S::NP];
+#pragma unroll
+  for (int f = 0; f <= D; ++f)
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i) acc[f][i] = 0.0;
+  double vx[D + 1][D];
+#pragma unroll
+  for (int k = 0; k <= D; ++k)
+#pragma unroll
+    for (int a = 0; a < D; ++a) vx[k][a] = m.vert[(size_t)(k * D + a) * n + e];
+#pragma unroll
+  for (int q = 0; q < S::NQ; ++q) {
+    double x, y = 0.0;
+    if (D == 1) {
+      x = vx[0][0] + 0.5 * (qxi[2 * q] + 1.0) * (vx[1][0] - vx[0][0]);
+    } else {
+      const double s = qxi[2 * q], t = qxi[2 * q + 1];
+      x = vx[0][0] + s * (vx[1][0] - vx[0][0]) + t * (vx[D][0] - vx[0][0]);
+      y = vx[0][D - 1] + s * (vx[1][D - 1] - vx[0][D - 1]) + t * (vx[D][D - 1] - vx[0][D - 1]);
+    }
+    double h, u, v;
+    ic_eval(ic, D, x, y, h, u, v);
+    const double val[3] = {h, u, v};
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i) {
+      const double c = (double)tb.qw[q] * (double)tb.phi[q][i];
+#pragma unroll
+      for (int f = 0; f <= D; ++f) acc[f][i] += c * val[f];
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < S::NF; ++f)
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i) W[(size_t)(f * S::NP + i) * n + e] = f <= D ? (T)acc[f][i] : T(0);
+}
+
+// raw (unfactored) blocks [bs][bs][n] -> row-major per element [n][bs][bs]
+template <class T>
+__global__ void __launch_bounds__(256) k_blocks_export(const T* __restrict__ A, T* __restrict__ out, int bs, int n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)bs * bs * n;
+  if (idx >= tot) return;
+  const int e = (int)(idx % n);
+  const int64_t rc = idx / n;
+  out[(size_t)e * bs * bs + rc] = A[idx];
+}
+
+// ---------------------------------------------------------------- reductions (host helpers)
+int ensure_part(bsw_disc d, size_t len) {
+  if (d->part_len >= len) return BSW_OK;
+  bsw_ctx c = d->mesh->ctx;
+  hfree(d->part);
+  d->part = nullptr;
+  d->part_len = 0;
+  if (int rc = dev_alloc(c, &d->part, len)) return rc;
+  d->part_len = len;
+  return BSW_OK;
+}
+
+int red_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + kRedThreads - 1) / kRedThreads)); }
+
+// finish a partial reduction of nv values into host out[]
+int finish(bsw_disc d, int nblk, int nv, const int* ops, double* host_out) {
+  bsw_ctx c = d->mesh->ctx;
+  hipLaunchKernelGGL(k_reduce_final, dim3(nv), dim3(kRedThreads), 0, c->stream, d->part, nblk, nullptr, ops[0],
+                     nv > 1 ? ops[1] : 0, nv > 2 ? ops[2] : 0, nv > 3 ? ops[3] : 0, d->red_out);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(d->red_host, d->red_out, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < nv; ++k) host_out[k] = d->red_host[k];
+  return BSW_OK;
+}
+
+// --------------------------------------------------------------- kernel launchers
+struct OpLaunch {
+  bsw_disc d; const bsw_params* p; double dt; const void* W; const void* bold; void* R;
+  template <int D, int P, class T>
+  int operator()() {
+    auto m = view<T>(d);
+    hipLaunchKernelGGL((k_operator<D, P, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream, (const T*)W,
+                       (const T*)bold, (T*)R, m, devparams<T>(*p, dt));
+    HIPCHK(d->mesh->ctx, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+struct StepBeginLaunch {
+  bsw_disc d; const bsw_params* p; double dt; const void* W; void* bold;
+  template <int D, int P, class T>
+  int operator()() {
+    auto m = view<T>(d);
+    hipLaunchKernelGGL((k_step_begin<D, P, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream, (const T*)W,
+                       (T*)bold, m, devparams<T>(*p, dt));
+    HIPCHK(d->mesh->ctx, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+struct JacApplyLaunch {
+  bsw_disc d; const void* x; void* y;
+  template <int D, int P, class T>
+  int operator()() {
+    auto m = view<T>(d);
+    hipLaunchKernelGGL((k_jac_apply<D, P, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream,
+                       (const T*)d->lin_W, (const T*)x, (T*)y, m, devparams<T>(d->lin_prm, d->lin_dt));
+    HIPCHK(d->mesh->ctx, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+struct LinearizeLaunch {
+  bsw_disc d;
+  template <int D, int P, class T>
+  int operator()() {
+    using S = Shape<D, P>;
+    auto m = view<T>(d);
+    bsw_ctx c = d->mesh->ctx;
+    dim3 gcols((unsigned)((m.n_el + 255) / 256), (unsigned)S::BS);
+    hipLaunchKernelGGL((k_jac_columns<D, P, T>), gcols, dim3(256), 0, c->stream, (const T*)d->lin_W,
+                       (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt));
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(d->blocks, d->blocks_raw, sizeof(T) * (size_t)S::BS * S::BS * m.n_el,
+                             hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL((k_block_lu<S::BS, T>), grid1(m.n_el), dim3(256), 0, c->stream, (T*)d->blocks, d->perm,
+                       m.n_el);
+    HIPCHK(c, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+struct PrecLaunch {
+  bsw_disc d; const void* x; void* y;
+  template <int D, int P, class T>
+  int operator()() {
+    using S = Shape<D, P>;
+    auto m = view<T>(d);
+    hipLaunchKernelGGL((k_block_solve<S::BS, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream,
+                       (const T*)d->blocks, d->perm, (const T*)x, (T*)y, m.n_el);
+    HIPCHK(d->mesh->ctx, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+struct DiagLaunch {
+  bsw_disc d; const bsw_params* p; const void* W; int nblk;
+  template <int D, int P, class T>
+  int operator()() {
+    auto m = view<T>(d);
+    const double thr = p->sigma0 / p->gamma;
+    hipLaunchKernelGGL((k_diag<D, P, T>), dim3(nblk), dim3(kRedThreads), 0, d->mesh->ctx->stream, (const T*)W, m,
+                       p->g, thr, d->part);
+    HIPCHK(d->mesh->ctx, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+struct ICLaunch {
+  bsw_disc d; bsw_ic ic; void* W; double* qxi;
+  template <int D, int P, class T>
+  int operator()() {
+    auto m = view<T>(d);
+    hipLaunchKernelGGL((k_project_ic<D, P, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream, (T*)W, m, ic, qxi);
+    HIPCHK(d->mesh->ctx, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+// ---------------------------------------------------------------- table staging
+template <int D, int P, class T>
+void fill_tab(const RefElement& R, Tab<D, P, T>& t) {
+  using S = Shape<D, P>;
+  for (int q = 0; q < S::NQ; ++q) {
+    t.qw[q] = (T)R.qw[q];
+    for (int i = 0; i < S::NP; ++i) {
+      t.phi[q][i] = (T)R.phi[q * S::NP + i];
+      for (int r = 0; r < D; ++r) t.dphi[q][i][r] = (T)R.dphi[(q * S::NP + i) * 2 + r];
+    }
+  }
+  for (int f = 0; f < S::NFC; ++f)
+    for (int r = 0; r < S::NFQ; ++r)
+      for (int i = 0; i < S::NP; ++i) t.fphi[f][r][i] = (T)R.fphi[(f * S::NFQ + r) * S::NP + i];
+  for (int r = 0; r < S::NFQ; ++r) t.fw[r] = (T)R.fw[r];
+}
+
+struct StageTables {
+  bsw_disc d;
+  template <int D, int P, class T>
+  int operator()() {
+    bsw_ctx c = d->mesh->ctx;
+    const RefElement& R = d->ref;
+    if (R.np != Shape<D, P>::NP || R.nq != Shape<D, P>::NQ || R.nfq != Shape<D, P>::NFQ)
+      return fail(c, BSW_E_ARG, "reference element does not match the compiled shape");
+    Tab<D, P, T> t;
+    fill_tab<D, P, T>(R, t);
+    HIPCHK(c, hipMemcpyToSymbol(HIP_SYMBOL(c_tables), &t, sizeof(t), tab_offset_rt(D, P, sizeof(T) == 4),
+                                hipMemcpyHostToDevice));
+    return BSW_OK;
+  }
+};
+
+// ---------------------------------------------------------------- GMRES + Newton
+template <class T>
+struct Solver {
+  bsw_disc d;
+  int64_t n;
+  T* V = nullptr;      // (m+1) x n Krylov basis
+  T* w = nullptr;      // work vector
+  T* z = nullptr;      // work vector
+  size_t m = 30;
+  double* hdev = nullptr;
+  double hh[80];
+
+  int dots(int k, const T* x, double* host_out) {
+    bsw_ctx c = d->mesh->ctx;
+    const int nblk = red_blocks(n);
+    if (int rc = ensure_part(d, (size_t)nblk * (k + 1))) return rc;
+    hipLaunchKernelGGL((k_multidot<T>), dim3(nblk, k), dim3(kRedThreads), 0, c->stream, V, (size_t)n, x, n, d->part);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows, dim3(k), dim3(kRedThreads), 0, c->stream, d->part, nblk, hdev);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(d->red_host, hdev, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int j = 0; j < k; ++j) host_out[j] = d->red_host[j];
+    return BSW_OK;
+  }
+  int norm(const T* x, double* out) {
+    bsw_ctx c = d->mesh->ctx;
+    const int nblk = red_blocks(n);
+    if (int rc = ensure_part(d, (size_t)nblk)) return rc;
+    hipLaunchKernelGGL((k_multidot<T>), dim3(nblk, 1), dim3(kRedThreads), 0, c->stream, x, (size_t)n, x, n, d->part);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kRedThreads), 0, c->stream, d->part, nblk, hdev);
+    HIPCHK(c, hipMemcpyAsync(d->red_host, hdev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *out = std::sqrt(d->red_host[0]);
+    return BSW_OK;
+  }
+  int multi_axpy(T* y, int k, const double* hcoef, double sgn) {
+    bsw_ctx c = d->mesh->ctx;
+    Coef cf;
+    for (int j = 0; j < 65; ++j) cf.h[j] = j < k ? hcoef[j] : 0.0;
+    hipLaunchKernelGGL((k_multi_axpy<T>), grid1(n), dim3(256), 0, c->stream, y, V, (size_t)n, k, cf, sgn, n);
+    HIPCHK(c, hipGetLastError());
+    return BSW_OK;
+  }
+
+  // Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt done
+  // twice: solves J x = b to ||b - J x|| <= rtol ||b|| (x starts at 0).
+  int gmres(const T* b, T* x, double rtol, int max_iters, int* iters, double* relres) {
+    bsw_ctx c = d->mesh->ctx;
+    *iters = 0;
+    HIPCHK(c, hipMemsetAsync(x, 0, sizeof(T) * n, c->stream));
+    double bn;
+    if (int rc = norm(b, &bn)) return rc;
+    *relres = 0.0;
+    if (bn == 0.0) return BSW_OK;
+    const int M = (int)m;
+    std::vector<double> H((M + 1) * M), cs(M), sn(M), g(M + 1), y(M);
+    double beta = bn;
+    // r = b
+    hipLaunchKernelGGL((k_scale_copy<T>), grid1(n), dim3(256), 0, c->stream, b, V, 1.0 / beta, n);
+    while (true) {
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int j = 0;
+      bool done = false;
+      for (j = 0; j < M && *iters < max_iters; ++j) {
+        PrecLaunch pl{d, V + (size_t)j * n, z};
+        if (int rc = dispatch(d, pl)) return rc;
+        JacApplyLaunch ja{d, z, w};
+        if (int rc = dispatch(d, ja)) return rc;
+        ++*iters;
+        double h1[80], h2[80];
+        if (int rc = dots(j + 1, w, h1)) return rc;
+        if (int rc = multi_axpy(w, j + 1, h1, -1.0)) return rc;
+        if (int rc = dots(j + 1, w, h2)) return rc;
+        if (int rc = multi_axpy(w, j + 1, h2, -1.0)) return rc;
+        for (int i = 0; i <= j; ++i) H[i * M + j] = h1[i] + h2[i];
+        double hn;
+        if (int rc = norm(w, &hn)) return rc;
+        H[(j + 1) * M + j] = hn;
+        if (hn > 0)
+          hipLaunchKernelGGL((k_scale_copy<T>), grid1(n), dim3(256), 0, c->stream, w, V + (size_t)(j + 1) * n,
+                             1.0 / hn, n);
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[i] * H[i * M + j] + sn[i] * H[(i + 1) * M + j];
+          H[(i + 1) * M + j] = -sn[i] * H[i * M + j] + cs[i] * H[(i + 1) * M + j];
+          H[i * M + j] = t;
+        }
+        const double den = std::hypot(H[j * M + j], H[(j + 1) * M + j]);
+        cs[j] = H[j * M + j] / den;
+        sn[j] = H[(j + 1) * M + j] / den;
+        H[j * M + j] = den;
+        H[(j + 1) * M + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        if (std::fabs(g[j + 1]) <= rtol * bn || hn == 0.0) { ++j; done = true; break; }
+      }
+      // x += M^{-1} (V y)
+      for (int i = j - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k < j; ++k) s -= H[i * M + k] * y[k];
+        y[i] = s / H[i * M + i];
+      }
+      HIPCHK(c, hipMemsetAsync(z, 0, sizeof(T) * n, c->stream));
+      if (int rc = multi_axpy(z, j, y.data(), 1.0)) return rc;
+      PrecLaunch pl{d, z, w};
+      if (int rc = dispatch(d, pl)) return rc;
+      hipLaunchKernelGGL((k_axpby<T>), grid1(n), dim3(256), 0, c->stream, x, 1.0, x, 1.0, w, n);
+      // true residual r = b - J x -> V[0]
+      JacApplyLaunch ja{d, x, w};
+      if (int rc = dispatch(d, ja)) return rc;
+      hipLaunchKernelGGL((k_axpby<T>), grid1(n), dim3(256), 0, c->stream, V, 1.0, b, -1.0, w, n);
+      if (int rc = norm(V, &beta)) return rc;
+      *relres = beta / bn;
+      if (done || beta <= rtol * bn || *iters >= max_iters) break;
+      hipLaunchKernelGGL((k_scale_copy<T>), grid1(n), dim3(256), 0, c->stream, V, V, 1.0 / beta, n);
+    }
+    return BSW_OK;
+  }
+};
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int bsw_ctx_create(int device, void* hip_stream, bsw_ctx* out) {
+  if (!out) return fail(nullptr, BSW_E_ARG, "out is null");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, BSW_E_ARG, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, BSW_E_HIP, "hipSetDevice failed");
+  bsw_ctx c = new bsw_ctx_s();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return BSW_OK;
+}
+
+int bsw_ctx_destroy(bsw_ctx c) {
+  delete c;
+  return BSW_OK;
+}
+
+const char* bsw_last_error(bsw_ctx c) { return c ? c->err.c_str() : g_err_no_ctx.c_str(); }
+
+int bsw_mesh_upload(bsw_ctx c, int dim, int64_t n_vert, const double* xy, int64_t n_el, const int32_t* e2v,
+                    bsw_mesh* out) {
+  if (!c || !out || !xy || !e2v) return fail(c, BSW_E_ARG, "null argument");
+  if ((dim != 1 && dim != 2) || n_vert < 2 || n_el < 1 || n_el > (int64_t(1) << 29))
+    return fail(c, BSW_E_ARG, "bad mesh sizes");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int nvpe = dim + 1, nfc = dim + 1;
+  for (int64_t k = 0; k < n_el * nvpe; ++k)
+    if (e2v[k] < 0 || e2v[k] >= n_vert) return fail(c, BSW_E_ARG, "vertex index out of range");
+  const int64_t n = n_el;
+  std::vector<double> dxi(dim * dim * n), detJ(n), nrm(nfc * dim * n), hlen(nfc * n), vert((dim + 1) * dim * n);
+  std::vector<int> nbr(nfc * n, -1);
+  double hmin = 1e300, meas = 0.0;
+  for (int64_t e = 0; e < n; ++e) {
+    const int32_t* v = e2v + e * nvpe;
+    for (int k = 0; k <= dim; ++k)
+      for (int a = 0; a < dim; ++a) vert[(k * dim + a) * n + e] = xy[(int64_t)v[k] * dim + a];
+    if (dim == 1) {
+      const double L = xy[v[1]] - xy[v[0]];
+      if (!(L > 0)) return fail(c, BSW_E_MESH, "non-positive segment length");
+      detJ[e] = 0.5 * L;
+      dxi[e] = 2.0 / L;
+      nrm[0 * n + e] = -1.0;
+      nrm[1 * n + e] = 1.0;
+      hlen[0 * n + e] = hlen[1 * n + e] = 1.0;
+      hmin = std::min(hmin, L);
+      meas += L;
+    } else {
+      const double x0 = xy[2 * v[0]], y0 = xy[2 * v[0] + 1];
+      const double x1 = xy[2 * v[1]], y1 = xy[2 * v[1] + 1];
+      const double x2 = xy[2 * v[2]], y2 = xy[2 * v[2] + 1];
+      const double j11 = x1 - x0, j12 = x2 - x0, j21 = y1 - y0, j22 = y2 - y0;
+      const double det = j11 * j22 - j12 * j21;
+      if (!(det > 0)) return fail(c, BSW_E_MESH, "triangle with non-positive orientation");
+      detJ[e] = det;
+      // inverse of the affine map's Jacobian: rows (dxi/dx, dxi/dy), (deta/dx, deta/dy)
+      dxi[0 * n + e] = j22 / det;
+      dxi[1 * n + e] = -j12 / det;
+      dxi[2 * n + e] = -j21 / det;
+      dxi[3 * n + e] = j11 / det;
+      const double X[3] = {x0, x1, x2}, Y[3] = {y0, y1, y2};
+      double lmax = 0.0;
+      for (int f = 0; f < 3; ++f) {
+        const double ex = X[(f + 1) % 3] - X[f], ey = Y[(f + 1) % 3] - Y[f];
+        const double L = std::sqrt(ex * ex + ey * ey);
+        nrm[(f * 2 + 0) * n + e] = ey / L;
+        nrm[(f * 2 + 1) * n + e] = -ex / L;
+        hlen[f * n + e] = 0.5 * L;
+        lmax = std::max(lmax, L);
+      }
+      hmin = std::min(hmin, det / lmax);
+      meas += 0.5 * det;
+    }
+  }
+  // faces: key = sorted vertex pair (2-D) or the vertex (1-D)
+  std::unordered_map<uint64_t, int64_t> open;
+  open.reserve((size_t)(n * nfc));
+  for (int64_t e = 0; e < n; ++e)
+    for (int f = 0; f < nfc; ++f) {
+      const int32_t* v = e2v + e * nvpe;
+      uint64_t key;
+      if (dim == 1) key = (uint64_t)v[f];
+      else {
+        const uint64_t a = (uint64_t)v[f], b = (uint64_t)v[(f + 1) % 3];
+        key = std::min(a, b) * (uint64_t)n_vert + std::max(a, b);
+      }
+      auto it = open.find(key);
+      if (it == open.end()) {
+        open.emplace(key, e * nfc + f);
+      } else {
+        const int64_t other = it->second;
+        if (other < 0) return fail(c, BSW_E_MESH, "face shared by more than two elements");
+        const int64_t oe = other / nfc;
+        const int of = (int)(other % nfc);
+        nbr[f * n + e] = (int)(oe * 4 + of);
+        nbr[of * n + oe] = (int)(e * 4 + f);
+        it->second = -1;
+      }
+    }
+  bsw_mesh M = new bsw_mesh_s();
+  M->ctx = c; M->dim = dim; M->nfc = nfc; M->n_el = n; M->n_vert = n_vert; M->hmin = hmin; M->measure = meas;
+  auto up = [&](auto** dst, auto& src) -> int {
+    using V = std::remove_pointer_t<std::remove_reference_t<decltype(*dst)>>;
+    if (int rc = dev_alloc(c, dst, src.size())) return rc;
+    HIPCHK(c, hipMemcpy(*dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice));
+    return BSW_OK;
+  };
+  int rc = BSW_OK;
+  if (!rc) rc = up(&M->nbr, nbr);
+  if (!rc) rc = up(&M->vert, vert);
+  if (!rc) rc = up(&M->m64.dxi, dxi);
+  if (!rc) rc = up(&M->m64.detJ, detJ);
+  if (!rc) rc = up(&M->m64.nrm, nrm);
+  if (!rc) rc = up(&M->m64.hlen, hlen);
+  if (rc) { bsw_mesh_destroy(M); return rc; }
+  M->h_dxi = std::move(dxi); M->h_detJ = std::move(detJ); M->h_nrm = std::move(nrm); M->h_hlen = std::move(hlen);
+  *out = M;
+  return BSW_OK;
+}
+
+int bsw_mesh_destroy(bsw_mesh M) {
+  if (!M) return BSW_OK;
+  hfree(M->nbr); hfree(M->vert);
+  hfree(M->m64.dxi); hfree(M->m64.detJ); hfree(M->m64.nrm); hfree(M->m64.hlen);
+  hfree(M->m32.dxi); hfree(M->m32.detJ); hfree(M->m32.nrm); hfree(M->m32.hlen);
+  delete M;
+  return BSW_OK;
+}
+
+int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
+  if (!M || !out) return fail(M ? M->ctx : nullptr, BSW_E_ARG, "null argument");
+  bsw_ctx c = M->ctx;
+  if (precision != BSW_FP64 && precision != BSW_FP32) return fail(c, BSW_E_ARG, "precision must be FP64 or FP32");
+  if (combo_index(M->dim, P) < 0) return fail(c, BSW_E_ARG, "unsupported order for this dimension");
+  HIPCHK(c, hipSetDevice(c->device));
+  bsw_disc d = new bsw_disc_s();
+  d->mesh = M; d->P = P; d->precision = precision;
+  d->wsize = precision == BSW_FP64 ? 8 : 4;
+  if (!build_reference(M->dim, P, d->ref)) { delete d; return fail(c, BSW_E_ARG, "reference element"); }
+  d->bs = d->ref.nf * d->ref.np;
+  // FP32 geometry view on first use
+  if (precision == BSW_FP32 && !M->m32.dxi) {
+    auto upf = [&](float** dst, const std::vector<double>& src) -> int {
+      std::vector<float> tmp(src.begin(), src.end());
+      if (int rc = dev_alloc(c, dst, tmp.size())) return rc;
+      HIPCHK(c, hipMemcpy(*dst, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice));
+      return BSW_OK;
+    };
+    int rc = upf(&M->m32.dxi, M->h_dxi);
+    if (!rc) rc = upf(&M->m32.detJ, M->h_detJ);
+    if (!rc) rc = upf(&M->m32.nrm, M->h_nrm);
+    if (!rc) rc = upf(&M->m32.hlen, M->h_hlen);
+    if (rc) { delete d; return rc; }
+  }
+  const int ci = combo_index(M->dim, P);
+  if (!c->tables_staged[precision][ci]) {
+    StageTables st{d};
+    if (int rc = dispatch(d, st)) { delete d; return rc; }
+    c->tables_staged[precision][ci] = true;
+  }
+  int rc = dev_alloc(c, &d->red_out, 64);
+  if (!rc) rc = dev_alloc(c, &d->hcoef, 80);
+  if (!rc && hipHostMalloc((void**)&d->red_host, 80 * sizeof(double)) != hipSuccess)
+    rc = fail(c, BSW_E_OOM, "hipHostMalloc");
+  if (rc) { bsw_disc_destroy(d); return rc; }
+  *out = d;
+  return BSW_OK;
+}
+
+int bsw_disc_destroy(bsw_disc d) {
+  if (!d) return BSW_OK;
+  hfree(d->blocks); hfree(d->blocks_raw); hfree(d->perm); hfree(d->part); hfree(d->red_out);
+  hfree(d->gm); hfree(d->hcoef);
+  if (d->red_host) (void)hipHostFree(d->red_host);
+  delete d;
+  return BSW_OK;
+}
+
+int bsw_disc_info(bsw_disc d, int64_t* info) {
+  if (!d || !info) return BSW_E_ARG;
+  info[0] = d->mesh->dim; info[1] = d->P; info[2] = d->ref.np; info[3] = d->ref.nq; info[4] = d->ref.nfq;
+  info[5] = d->ref.nfc; info[6] = d->ref.nf; info[7] = d->mesh->n_el;
+  return BSW_OK;
+}
+
+int64_t bsw_state_len(bsw_disc d) { return d ? (int64_t)d->bs * d->mesh->n_el : -1; }
+
+int bsw_project_ic(bsw_disc d, const bsw_ic* ic, void* W) {
+  if (!d || !ic || !W) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  bsw_ctx c = d->mesh->ctx;
+  double* qxi = nullptr;
+  if (int rc = dev_alloc(c, &qxi, d->ref.qxi.size())) return rc;
+  HIPCHK(c, hipMemcpy(qxi, d->ref.qxi.data(), sizeof(double) * d->ref.qxi.size(), hipMemcpyHostToDevice));
+  ICLaunch L{d, *ic, W, qxi};
+  int rc = dispatch(d, L);
+  (void)hipStreamSynchronize(c->stream);
+  hfree(qxi);
+  return rc;
+}
+
+int bsw_step_begin(bsw_disc d, const bsw_params* p, double dt, const void* Wold, void* bold) {
+  if (!d || !Wold || !bold || !(dt > 0)) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "bad argument");
+  if (int rc = check_params(d, p)) return rc;
+  StepBeginLaunch L{d, p, dt, Wold, bold};
+  return dispatch(d, L);
+}
+
+int bsw_operator_apply(bsw_disc d, const bsw_params* p, double dt, const void* W, const void* bold, void* R) {
+  if (!d || !W || !bold || !R || !(dt > 0)) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "bad argument");
+  if (W == R || bold == R) return fail(d->mesh->ctx, BSW_E_ARG, "R must not alias W or b_old");
+  if (int rc = check_params(d, p)) return rc;
+  OpLaunch L{d, p, dt, W, bold, R};
+  return dispatch(d, L);
+}
+
+int bsw_jacobian_linearize(bsw_disc d, const bsw_params* p, double dt, const void* W) {
+  if (!d || !W || !(dt > 0)) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "bad argument");
+  if (int rc = check_params(d, p)) return rc;
+  bsw_ctx c = d->mesh->ctx;
+  const size_t nb = (size_t)d->bs * d->bs * d->mesh->n_el;
+  if (!d->blocks) {
+    if (hipMalloc(&d->blocks, nb * d->wsize) != hipSuccess || hipMalloc(&d->blocks_raw, nb * d->wsize) != hipSuccess ||
+        hipMalloc((void**)&d->perm, sizeof(int) * d->bs * d->mesh->n_el) != hipSuccess)
+      return fail(c, BSW_E_OOM, "block-Jacobi storage");
+  }
+  d->lin_W = W;
+  d->lin_prm = *p;
+  d->lin_dt = dt;
+  LinearizeLaunch L{d};
+  return dispatch(d, L);
+}
+
+int bsw_jacobian_apply(bsw_disc d, const void* x, void* y) {
+  if (!d || !x || !y) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  if (!d->lin_W) return fail(d->mesh->ctx, BSW_E_STATE, "jacobian_apply before jacobian_linearize");
+  if (x == y) return fail(d->mesh->ctx, BSW_E_ARG, "x and y must not alias");
+  JacApplyLaunch L{d, x, y};
+  return dispatch(d, L);
+}
+
+int bsw_precond_apply(bsw_disc d, const void* x, void* y) {
+  if (!d || !x || !y) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  if (!d->lin_W) return fail(d->mesh->ctx, BSW_E_STATE, "precond_apply before jacobian_linearize");
+  if (x == y) return fail(d->mesh->ctx, BSW_E_ARG, "x and y must not alias");
+  PrecLaunch L{d, x, y};
+  return dispatch(d, L);
+}
+
+int bsw_jacobian_blocks(bsw_disc d, void* blocks) {
+  if (!d || !blocks) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  if (!d->lin_W) return fail(d->mesh->ctx, BSW_E_STATE, "jacobian_blocks before jacobian_linearize");
+  bsw_ctx c = d->mesh->ctx;
+  const int64_t tot = (int64_t)d->bs * d->bs * d->mesh->n_el;
+  if (d->precision == BSW_FP64)
+    hipLaunchKernelGGL((k_blocks_export<double>), grid1(tot), dim3(256), 0, c->stream, (const double*)d->blocks_raw,
+                       (double*)blocks, d->bs, (int)d->mesh->n_el);
+  else
+    hipLaunchKernelGGL((k_blocks_export<float>), grid1(tot), dim3(256), 0, c->stream, (const float*)d->blocks_raw,
+                       (float*)blocks, d->bs, (int)d->mesh->n_el);
+  HIPCHK(c, hipGetLastError());
+  return BSW_OK;
+}
+
+int bsw_stage_update(bsw_disc d, const bsw_params* p, void* W, const void* dW, double alpha, double* norms_out) {
+  if (!d || !W || !dW) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  bsw_ctx c = d->mesh->ctx;
+  const int64_t n = bsw_state_len(d);
+  const int nblk = red_blocks(n);
+  if (int rc = ensure_part(d, (size_t)nblk * 4)) return rc;
+  if (d->precision == BSW_FP64)
+    hipLaunchKernelGGL((k_axpy_norms<double>), dim3(nblk), dim3(kRedThreads), 0, c->stream, (double*)W,
+                       (const double*)dW, alpha, n, d->part);
+  else
+    hipLaunchKernelGGL((k_axpy_norms<float>), dim3(nblk), dim3(kRedThreads), 0, c->stream, (float*)W,
+                       (const float*)dW, alpha, n, d->part);
+  HIPCHK(c, hipGetLastError());
+  if (!norms_out) return BSW_OK;
+  const int ops[2] = {1, 1};
+  if (int rc = finish(d, nblk, 2, ops, norms_out)) return rc;
+  if (p) {
+    double dg[4];
+    if (int rc = bsw_diagnostics(d, p, W, dg)) return rc;
+    norms_out[2] = dg[0];
+    norms_out[3] = dg[1];
+  } else {
+    norms_out[2] = norms_out[3] = 0.0;
+  }
+  return BSW_OK;
+}
+
+int bsw_diagnostics(bsw_disc d, const bsw_params* p, const void* W, double* out4) {
+  if (!d || !p || !W || !out4) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  const int nblk = red_blocks(d->mesh->n_el);
+  if (int rc = ensure_part(d, (size_t)nblk * 4)) return rc;
+  DiagLaunch L{d, p, W, nblk};
+  if (int rc = dispatch(d, L)) return rc;
+  const int ops[4] = {0, 0, 1, 2};
+  if (int rc = finish(d, nblk, 4, ops, out4)) return rc;
+  out4[1] = 100.0 * out4[1] / d->mesh->measure;
+  return BSW_OK;
+}
+
+int bsw_norm2(bsw_disc d, const void* x, double* out) {
+  if (!d || !x || !out) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  bsw_ctx c = d->mesh->ctx;
+  const int64_t n = bsw_state_len(d);
+  const int nblk = red_blocks(n);
+  if (int rc = ensure_part(d, (size_t)nblk)) return rc;
+  if (d->precision == BSW_FP64)
+    hipLaunchKernelGGL((k_multidot<double>), dim3(nblk, 1), dim3(kRedThreads), 0, c->stream, (const double*)x,
+                       (size_t)n, (const double*)x, n, d->part);
+  else
+    hipLaunchKernelGGL((k_multidot<float>), dim3(nblk, 1), dim3(kRedThreads), 0, c->stream, (const float*)x,
+                       (size_t)n, (const float*)x, n, d->part);
+  HIPCHK(c, hipGetLastError());
+  const int ops[1] = {0};
+  double s;
+  if (int rc = finish(d, nblk, 1, ops, &s)) return rc;
+  *out = std::sqrt(s);
+  return BSW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- whole solve
+namespace {
+
+template <class T>
+int solve_impl(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, bsw_solve_stats* st) {
+  bsw_ctx c = d->mesh->ctx;
+  const int64_t n = bsw_state_len(d);
+  const int M = std::max(1, std::min(64, o->gmres_m));
+  // workspace: V (M+1), w, z, R, Rt, rhs, dW, Wt, bold
+  const size_t need = (size_t)(M + 1 + 8) * n * sizeof(T);
+  if (d->gm_bytes < need) {
+    hfree(d->gm);
+    d->gm = nullptr;
+    d->gm_bytes = 0;
+    if (hipMalloc(&d->gm, need) != hipSuccess) return fail(c, BSW_E_OOM, "solver workspace");
+    d->gm_bytes = need;
+  }
+  T* base = (T*)d->gm;
+  Solver<T> S;
+  S.d = d; S.n = n; S.m = M; S.V = base; S.hdev = d->hcoef;
+  T* w = base + (size_t)(M + 1) * n;
+  T* z = w + n;
+  T* R = z + n;
+  T* Rt = R + n;
+  T* rhs = Rt + n;
+  T* dW = rhs + n;
+  T* Wt = dW + n;
+  T* bold = Wt + n;
+  S.w = w; S.z = z;
+  auto t0 = std::chrono::steady_clock::now();
+  std::memset(st, 0, sizeof(*st));
+  double dg[4];
+  if (int rc = bsw_diagnostics(d, p, W, dg)) return rc;
+  st->mass0 = dg[0];
+  double dt = o->dt > 0 ? o->dt : o->cfl * d->mesh->hmin / dg[2];
+  st->dt = dt;
+  const int n_total = std::max(1, (int)std::ceil(o->t_end / dt - 1e-12));
+  const int nsteps = o->max_steps < 0 ? n_total : std::min(n_total, o->max_steps);
+  double t = 0.0;
+  const int nblk = red_blocks(n);
+  int status = BSW_OK;
+  for (int k = 1; k <= nsteps; ++k) {
+    const double dtk = k < n_total ? dt : o->t_end - (k - 1) * dt;
+    if (int rc = bsw_step_begin(d, p, dtk, W, bold)) return rc;
+    if (int rc = bsw_operator_apply(d, p, dtk, W, bold, R)) return rc;
+    st->operator_applies += 1;
+    double rn;
+    if (int rc = bsw_norm2(d, R, &rn)) return rc;
+    int conv = 0, it = 0;
+    for (it = 1; it <= o->max_newton; ++it) {
+      if (int rc = bsw_jacobian_linearize(d, p, dtk, W)) return rc;
+      hipLaunchKernelGGL((k_scale_copy<T>), grid1(n), dim3(256), 0, c->stream, R, rhs, -1.0, n);
+      int gits = 0;
+      double relres = 0.0;
+      if (int rc = S.gmres(rhs, dW, o->gmres_rtol, o->gmres_max_iters, &gits, &relres)) return rc;
+      st->gmres_total += gits;
+      st->jacobian_applies += gits + 1;
+      // convergence test on the full Newton update
+      double nm[2];
+      {
+        if (int rc = ensure_part(d, (size_t)nblk * 4)) return rc;
+        hipLaunchKernelGGL((k_absmax<T>), dim3(nblk), dim3(kRedThreads), 0, c->stream, dW, n, d->part);
+        hipLaunchKernelGGL((k_absmax<T>), dim3(nblk), dim3(kRedThreads), 0, c->stream, W, n, d->part + nblk);
+        const int ops[2] = {1, 1};
+        if (int rc = finish(d, nblk, 2, ops, nm)) return rc;
+      }
+      if (std::isfinite(nm[0]) && nm[0] <= o->newton_tol * (1.0 + nm[1])) {
+        hipLaunchKernelGGL((k_axpby<T>), grid1(n), dim3(256), 0, c->stream, W, 1.0, W, 1.0, dW, n);
+        conv = 1;
+        break;
+      }
+      double a = 1.0, rnt = 0.0;
+      for (;;) {
+        hipLaunchKernelGGL((k_axpby<T>), grid1(n), dim3(256), 0, c->stream, Wt, 1.0, W, a, dW, n);
+        if (int rc = bsw_operator_apply(d, p, dtk, Wt, bold, Rt)) return rc;
+        st->operator_applies += 1;
+        if (int rc = bsw_norm2(d, Rt, &rnt)) return rc;
+        if ((std::isfinite(rnt) && rnt <= (1.0 - 1e-4 * a) * rn) || a <= 1.0 / 64.0) break;
+        a *= 0.5;
+      }
+      HIPCHK(c, hipMemcpyAsync(W, Wt, sizeof(T) * n, hipMemcpyDeviceToDevice, c->stream));
+      std::swap(R, Rt);
+      rn = rnt;
+      if (!std::isfinite(rnt)) { conv = -1; break; }
+    }
+    if (it > o->max_newton) it = o->max_newton;
+    st->newton_total += it;
+    st->newton_max = std::max(st->newton_max, it);
+    if (conv != 1) { st->capped += 1; status = BSW_W_NOT_CONVERGED; }
+    if (int rc = bsw_diagnostics(d, p, W, dg)) return rc;
+    st->max_mass_drift = std::max(st->max_mass_drift, std::fabs(dg[0] - st->mass0) / st->mass0);
+    t += dtk;
+    st->steps = k;
+    if (conv < 0) break;
+  }
+  st->mass_end = dg[0];
+  st->active_pct = dg[1];
+  st->t_end = t;
+  st->status = status;
+  st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return status;
+}
+
+}  // namespace
+
+extern "C" int bsw_solve(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, void* W, bsw_solve_stats* st) {
+  if (!d || !o || !W || !st) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  if (int rc = check_params(d, p)) return rc;
+  if (o->max_newton < 1 || o->gmres_max_iters < 1 || !(o->t_end > 0))
+    return fail(d->mesh->ctx, BSW_E_ARG, "bad solve options");
+  if (d->precision == BSW_FP64) return solve_impl<double>(d, p, o, (double*)W, st);
+  return solve_impl<float>(d, p, o, (float*)W, st);
+}

@@ -1,0 +1,199 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle on the
+same seeded inputs.  Meshes span several 256-element tiles with a ragged tail;
+all three regularisations, both dimensions, orders 0-4 (1-D) and 1-3
+(triangles), and the boundary kinds are covered.  FP64 bar: 1e-12 relative
+(max-norm per field) for single applies, 1e-10 relative L2 on h and h u after
+whole solves (the target the method states for the FP64 path)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from _gpu_util import Pair, have_gpu, mesh_for, relerr
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
+
+OP_CASES = [(1, 0, 50), (1, 1, 300), (1, 2, 257), (1, 3, 64), (1, 4, 40), (2, 1, 13), (2, 2, 13), (2, 3, 11)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2301_11238_amd import bsw
+    c = bsw.Context(0)
+    yield c
+    c.close()
+
+
+def make_pair(ctx, dim, P, n):
+    xy, e2v = mesh_for(dim, n)
+    return Pair(ctx, dim, P, xy, e2v)
+
+
+def prm_for(reg, alpha=0.12):
+    return wl.Params(g=9.81, rho=1000.0, alpha=alpha, eta=0.8, sigma0=40.0, gamma=1e3, beta=1e3, reg=reg)
+
+
+@pytest.mark.parametrize("dim,P,n", OP_CASES)
+def test_project_ic(ctx, dim, P, n):
+    pr = make_pair(ctx, dim, P, n)
+    ics = [wl.IC(kind=wl.IC_STEP_X, a=1.0, b=0.1, x0=5.3),
+           wl.IC(kind=wl.IC_MOUND, a=1.0, b=0.5, x0=10.0, y0=10.0, d=4.0)]
+    if dim == 2:
+        ics += [wl.IC(kind=wl.IC_VORTEX, a=1.0, b=0.3, L=20.0), wl.IC(kind=wl.IC_LINEAR_X, a=3.0, b=-0.1)]
+    else:
+        ics += [wl.IC(kind=wl.IC_SINE_U, a=1.0, b=0.3, L=10.0)]
+    for ic in ics:
+        Wg = pr.host(pr.disc.project_ic(ic))
+        Wo = pr.orc.project_ic(ic)
+        assert np.abs(Wg - Wo).max() <= 1e-13 * max(1.0, np.abs(Wo).max())
+
+
+@pytest.mark.parametrize("dim,P,n", OP_CASES)
+@pytest.mark.parametrize("reg", [1, 2, 3])
+def test_step_begin_and_operator(ctx, dim, P, n, reg):
+    from paper_2301_11238_amd import bsw
+    pr = make_pair(ctx, dim, P, n)
+    p = prm_for(reg)
+    W = wl.random_state(dim, P, pr.disc.n_el, 100 + reg)
+    Wold = wl.random_state(dim, P, pr.disc.n_el, 200 + reg)
+    dt = 0.0137
+    cp = bsw.make_params(p)
+    bg = pr.disc.step_begin(cp, dt, pr.dev(Wold))
+    bo = pr.orc.step_begin(p, Wold, dt)
+    assert relerr(pr.host(bg), bo[: 1 + dim]) <= 1e-13
+    Rg = pr.host(pr.disc.operator_apply(cp, dt, pr.dev(W), bg))
+    Ro = pr.orc.residual(p, W, bo, dt)
+    assert relerr(Rg, Ro) <= 1e-12
+
+
+@pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_DIRICHLET])
+@pytest.mark.parametrize("dim,P,n", [(1, 2, 70), (2, 2, 9)])
+def test_operator_other_boundaries(ctx, dim, P, n, bc):
+    from paper_2301_11238_amd import bsw
+    pr = make_pair(ctx, dim, P, n)
+    p = prm_for(1)
+    dirv = [1.1, 0.3, -0.2, 0.01, 0.02, -0.03, 0.04][: 1 + dim + dim * dim]
+    W = wl.random_state(dim, P, pr.disc.n_el, 5)
+    dt = 0.02
+    cp = bsw.make_params(p, bc=bc, dirichlet=dirv)
+    bo = pr.orc.step_begin(p, W * 0.9, dt)
+    Rg = pr.host(pr.disc.operator_apply(cp, dt, pr.dev(W), pr.dev(bo[: 1 + dim])))
+    Ro = pr.orc.residual(p, W, bo, dt, bc=bc, dirichlet=dirv)
+    assert relerr(Rg, Ro) <= 1e-12
+    pr.disc.jacobian_linearize(cp, dt, pr.dev(W))
+    x = wl.random_vector(dim, P, pr.disc.n_el, 6)
+    yg = pr.host(pr.disc.jacobian_apply(pr.dev(x)))
+    yo = pr.orc.jac_apply(p, W, x, dt, bc=bc, dirichlet=dirv)
+    assert relerr(yg, yo) <= 1e-11
+
+
+@pytest.mark.parametrize("dim,P,n", OP_CASES)
+@pytest.mark.parametrize("reg", [1, 3])
+def test_jacobian_apply_blocks_and_preconditioner(ctx, dim, P, n, reg):
+    from paper_2301_11238_amd import bsw
+    pr = make_pair(ctx, dim, P, n)
+    p = prm_for(reg)
+    W = wl.random_state(dim, P, pr.disc.n_el, 300 + reg)
+    x = wl.random_vector(dim, P, pr.disc.n_el, 301)
+    dt = 0.021
+    cp = bsw.make_params(p)
+    Wd = pr.dev(W)
+    pr.disc.jacobian_linearize(cp, dt, Wd)
+    yg = pr.host(pr.disc.jacobian_apply(pr.dev(x)))
+    yo = pr.orc.jac_apply(p, W, x, dt)
+    assert relerr(yg, yo) <= 1e-11
+    Bg = pr.host(pr.disc.jacobian_blocks())
+    Bo = pr.orc.jac_blocks(p, W, dt)
+    assert np.abs(Bg - Bo).max() <= 1e-12 * np.abs(Bo).max()
+    # preconditioner: block_e y_e = x_e
+    yp = pr.host(pr.disc.precond_apply(pr.dev(x)))
+    nf, np_, ne = pr.shape
+    xe = np.transpose(x, (2, 0, 1)).reshape(ne, nf * np_)
+    ye = np.transpose(yp, (2, 0, 1)).reshape(ne, nf * np_)
+    res = np.einsum("eij,ej->ei", Bo, ye) - xe
+    assert np.abs(res).max() <= 1e-10 * np.abs(xe).max()
+
+
+def test_stage_update_and_reductions(ctx):
+    from paper_2301_11238_amd import bsw
+    for dim, P, n in [(1, 1, 300), (2, 2, 13)]:
+        pr = make_pair(ctx, dim, P, n)
+        p = prm_for(2)
+        W = wl.random_state(dim, P, pr.disc.n_el, 9)
+        dW = wl.random_vector(dim, P, pr.disc.n_el, 10) * 1e-3
+        Wd = pr.dev(W)
+        norms = pr.disc.stage_update(bsw.make_params(p), Wd, pr.dev(dW), 0.5)
+        Wn = W + 0.5 * dW
+        assert np.abs(pr.host(Wd) - Wn).max() <= 1e-15 * np.abs(Wn).max()
+        assert norms[0] == pytest.approx(np.abs(0.5 * dW).max(), rel=1e-15)
+        assert norms[1] == pytest.approx(np.abs(Wn).max(), rel=1e-15)
+        dg = pr.orc.diagnostics(p, Wn)
+        assert norms[2] == pytest.approx(dg["mass"], rel=1e-13)
+        assert norms[3] == pytest.approx(dg["active_pct"], abs=1e-9)
+        d2 = pr.disc.diagnostics(bsw.make_params(p), pr.dev(Wn))
+        assert d2["lambda_max"] == pytest.approx(dg["lambda_max"], rel=1e-14)
+        assert d2["h_min"] == pytest.approx(dg["h_min"], rel=1e-14)
+        assert pr.disc.norm2(pr.dev(dW)) == pytest.approx(np.linalg.norm(dW), rel=1e-13)
+
+
+def rel_l2_h_hu(orc, Wa, Wb):
+    """relative L2 errors of h and of h*u (vector) at the volume points"""
+    t = orc.ref_tables()
+    md = orc.mesh_data()
+    w = (t["qw"][None, :] * md["detJ"][:, None])[..., None]
+    va, vb = orc.eval_points(Wa), orc.eval_points(Wb)
+    d = orc.dim
+    ha, hb = va[..., :1], vb[..., :1]
+    qa, qb = va[..., :1] * va[..., 1:1 + d], vb[..., :1] * vb[..., 1:1 + d]
+    eh = math.sqrt((w * (ha - hb) ** 2).sum() / (w * hb ** 2).sum())
+    eq = math.sqrt((w * (qa - qb) ** 2).sum() / max((w * qb ** 2).sum(), 1e-300))
+    return eh, eq
+
+
+SOLVES = [
+    # (name, dim, P, n, reg, sigma0, eta, eps, alpha, ic, t_end)
+    ("ritter_1d", 1, 1, 100, 1, 0.0, 0.0, 1e-3, 0.0, wl.IC(kind=wl.IC_STEP_X, a=1.0, b=0.1, x0=5.0), 0.1),
+    ("bingham_1d_reg1", 1, 1, 100, 1, 50.0, 1.0, 1e-2, 0.0, wl.IC(kind=wl.IC_STEP_X, a=1.0, b=0.1, x0=5.0), 0.05),
+    ("bingham_1d_reg3_p2", 1, 2, 60, 3, 5.0, 1.0, 1e-1, 0.0, wl.IC(kind=wl.IC_STEP_X, a=1.0, b=0.1, x0=5.0), 0.05),
+    ("mound_2d_reg2", 2, 2, 8, 2, 60.0, 1.0, 1e-2, math.atan(0.1),
+     wl.IC(kind=wl.IC_MOUND, a=1.0, b=0.5, x0=10.0, y0=10.0, d=4.0), 0.1),
+    ("mound_2d_reg1_p3", 2, 3, 6, 1, 30.0, 0.5, 1e-2, 0.0,
+     wl.IC(kind=wl.IC_MOUND, a=0.5, b=1.5, x0=10.0, y0=10.0, d=6.0), 0.25),
+]
+
+
+@pytest.mark.parametrize("case", SOLVES, ids=[c[0] for c in SOLVES])
+def test_whole_solve_matches_oracle(ctx, case):
+    import oracle
+    from paper_2301_11238_amd import bsw
+    name, dim, P, n, reg, s0, eta, eps, alpha, ic, t_end = case
+    pr = make_pair(ctx, dim, P, n)
+    p = wl.Params(g=9.81, rho=1000.0, alpha=alpha, eta=eta, sigma0=s0, gamma=1 / eps, beta=1 / eps, reg=reg)
+    W0 = pr.orc.project_ic(ic)
+    Wo, so = pr.orc.solve(p, W0, oracle.SolveOptions(t_end=t_end, cfl=0.2))
+    Wd = pr.dev(W0)
+    sg = pr.disc.solve(bsw.make_params(p), bsw.Options(t_end=t_end, cfl=0.2), Wd)
+    assert so["capped"] == 0 and sg["capped"] == 0, (so, sg)
+    assert sg["steps"] == so["steps"]
+    assert sg["dt"] == pytest.approx(so["dt"], rel=1e-14)
+    eh, eq = rel_l2_h_hu(pr.orc, pr.host(Wd), Wo)
+    assert eh <= 1e-10 and eq <= 1e-10, (eh, eq)
+    assert sg["max_mass_drift"] <= 1e-11
+
+
+def test_errors_are_reported(ctx):
+    from paper_2301_11238_amd import bsw
+    pr = make_pair(ctx, 2, 2, 3)
+    W = pr.dev(wl.random_state(2, 2, pr.disc.n_el, 1))
+    cp = bsw.make_params(prm_for(1))
+    with pytest.raises(bsw.BswError):
+        pr.disc.jacobian_apply(W)  # before linearize
+    with pytest.raises(bsw.BswError):
+        pr.disc.operator_apply(cp, 0.01, W, W[:3].contiguous(), W)  # R aliases W
+    bad = bsw.make_params(prm_for(1))
+    bad.reg = 4
+    with pytest.raises(bsw.BswError):
+        pr.disc.operator_apply(bad, 0.01, W, W[:3].contiguous())
+    with pytest.raises(bsw.BswError):
+        bsw.Disc(pr.mesh, 5)
