@@ -1,0 +1,187 @@
+"""Benchmark: implicit steps of the regularised-Bingham DG solver on one MI355X.
+
+Workload (the 2-D incline configuration): 64x64 jittered squares split into
+8192 triangles on a 20 m x 20 m domain, DG P2 (6 modes, 7-point rule), 10 %
+slope, Gaussian mound h = 1 + 0.5 exp(-r^2/4), regularisation 1 with
+eps = 1e-3 (gamma = beta = 1e3), yield stress drawn U[20, 200] Pa, FP64.
+Inputs are synthetic and seeded; the state sits in HBM before timing starts.
+
+One step = one backward-Euler time step: b_old, Newton iterations (operator
+apply, Jacobian linearisation and block LU, block-Jacobi GMRES with matrix-free
+Jacobian applies, backtracking, stage update) -- every row of the hot path.
+
+value = DOF-updates/s: degrees of freedom times the number of whole-mesh
+operator and Jacobian applies done in the timed steps, divided by the time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def bytes_per_element(dim, P, w):
+    """Algorithmic HBM bytes of one operator apply per element: read W (n_f N_p),
+    b_old (N_v N_p), write R (n_f N_p), the affine metric, normals and face
+    lengths (dim^2 + 1 + (dim+1)(dim+1) reals) and the neighbour codes."""
+    nf, nv = 1 + dim + dim * dim, 1 + dim
+    npm = P + 1 if dim == 1 else (P + 1) * (P + 2) // 2
+    nfc = dim + 1
+    geo = dim * dim + 1 + nfc * dim + nfc
+    return w * (2 * nf * npm + nv * npm + geo) + 4 * nfc
+
+
+def jac_bytes_per_element(dim, P, w):
+    """Matrix-free Jacobian apply: read W and x, write y, plus the geometry."""
+    nf = 1 + dim + dim * dim
+    npm = P + 1 if dim == 1 else (P + 1) * (P + 2) // 2
+    nfc = dim + 1
+    geo = dim * dim + 1 + nfc * dim + nfc
+    return w * (3 * nf * npm + geo) + 4 * nfc
+
+
+def time_kernel(fn, stream, reps=20):
+    import torch
+    fn()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / 1e3 / reps
+
+
+def cpu_baseline(problem, seconds):
+    """Oracle operator and Jacobian applies on the same mesh and state."""
+    import numpy as np
+    import oracle
+    import workloads as wl
+    orc = oracle.Oracle(problem.dim, problem.P, problem.xy, problem.el2vert)
+    W = orc.project_ic(problem.ic)
+    dt = 0.01
+    b = orc.step_begin(problem.params, W, dt)
+    x = wl.random_vector(problem.dim, problem.P, orc.n_el, 1)
+    n_dof = W.size
+    applies, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        orc.residual(problem.params, W, b, dt)
+        orc.jac_apply(problem.params, W, x, dt)
+        applies += 2
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=n_dof * applies / el, unit="DOF-updates/s", cores=threads, kind="oracle",
+                sample=f"{applies} whole-mesh applies (operator + Jacobian, alternating) of the FP64 C oracle "
+                       f"on the same 8192-triangle P2 mesh, {el:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as wl
+    from paper_2301_11238_amd import bsw
+
+    problem = wl.config2(wl.REG1, 1e-3)
+    ctx = bsw.Context(0)
+    stream = ctx.stream
+    mesh = bsw.Mesh(ctx, 2, problem.xy, problem.el2vert)
+    disc = bsw.Disc(mesh, problem.P, bsw.BSW_FP64)
+    cp = bsw.make_params(problem.params)
+    W = disc.project_ic(problem.ic)
+    dt = disc.cfl_dt(cp, W, problem.cfl)
+    n_dof = disc.state_len()
+
+    # warm-up steps, then exactly `steps` timed steps from where warm-up ended
+    if args.warmup > 0:
+        disc.solve(cp, bsw.Options(t_end=(args.warmup + 0.5) * dt, dt=dt, max_steps=args.warmup), W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = disc.solve(cp, bsw.Options(t_end=(args.steps + 0.5) * dt, dt=dt, max_steps=args.steps), W)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if st["steps"] != args.steps:
+        raise RuntimeError(f"solve stopped after {st['steps']} of {args.steps} steps: {st}")
+    applies = st["operator_applies"] + st["jacobian_applies"]
+    value = n_dof * applies / el
+
+    # live roofline of the operator and Jacobian kernels (HIP events on the library's stream)
+    b = disc.step_begin(cp, dt, W)
+    R = disc.empty()
+    t_op = time_kernel(lambda: disc.operator_apply(cp, dt, W, b, R), stream)
+    disc.jacobian_linearize(cp, dt, W)
+    x = torch.randn_like(W)
+    y = disc.empty()
+    t_jac = time_kernel(lambda: disc.jacobian_apply(x, y), stream)
+    t_pc = time_kernel(lambda: disc.precond_apply(x, y), stream)
+    n_el = disc.n_el
+    op_bytes = bytes_per_element(2, problem.P, 8) * n_el
+    jac_bytes = jac_bytes_per_element(2, problem.P, 8) * n_el
+    bs = disc.nf * disc.np
+    pc_bytes = (8 * bs * bs + 4 * bs + 2 * 8 * bs) * n_el
+    kern = {
+        "operator": dict(seconds=t_op, bytes=op_bytes),
+        "jacobian_apply": dict(seconds=t_jac, bytes=jac_bytes),
+        "block_jacobi_solve": dict(seconds=t_pc, bytes=pc_bytes),
+    }
+    dominant = "operator"
+    k = kern[dominant]
+    achieved = k["bytes"] / k["seconds"] / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_operator<2,2,double>",
+            "bytes_per_launch": k["bytes"], "launch_seconds": k["seconds"]}
+
+    out = {
+        "metric": "DG DOF-updates/s (+% HBM roofline); solves/s and p50/p99 latency, batched vs plain",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded jittered mesh, analytic initial mound)",
+        "config": {"workload": "2-D Bingham flow on a 10% incline, 64x64 jittered -> 8192 triangles, "
+                               "DG P2, reg 1, eps 1e-3, FP64, backward Euler at CFL 0.2",
+                   "n_el": n_el, "n_dof": n_dof, "dt": dt,
+                   "newton_per_step": st["newton_total"] / max(1, st["steps"]),
+                   "gmres_per_step": st["gmres_total"] / max(1, st["steps"]),
+                   "capped_steps": st["capped"],
+                   "applies_per_step": applies / max(1, st["steps"]),
+                   "dof_steps_per_s": n_dof * st["steps"] / el},
+        "roofline": roof,
+        "kernels": {name: {"ms": 1e3 * v["seconds"], "GB/s": v["bytes"] / v["seconds"] / 1e9}
+                    for name, v in kern.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -90,7 +90,9 @@ typedef struct {
   int32_t gmres_m;         /* GMRES restart length (<= 64) */
   int32_t gmres_max_iters; /* total GMRES iterations per Newton system */
   double newton_tol;       /* stop when ||dW||_inf <= newton_tol (1 + ||W||_inf) */
-  double gmres_rtol;       /* relative residual of each Newton system */
+  double gmres_rtol;       /* tightest relative residual asked of GMRES; each Newton
+                              system uses an Eisenstat-Walker forcing term in
+                              [gmres_rtol, 1e-3] */
   double cfl, t_end, dt;
   int32_t max_steps;       /* < 0: all steps */
 } bsw_solve_opts;
@@ -176,11 +178,15 @@ int bsw_stage_update(bsw_disc disc, const bsw_params* prm, void* W, const void* 
 int bsw_diagnostics(bsw_disc disc, const bsw_params* prm, const void* W, double* out4);
 /* *out (host) = sqrt(sum x^2) accumulated in FP64. */
 int bsw_norm2(bsw_disc disc, const void* x, double* out);
+/* *dt_out (host) = cfl * h_min / max(|u| + sqrt(g h)) over W's volume points,
+ * h_min the smallest element altitude (2-D) or length (1-D): the fixed time
+ * step a whole solve takes from its initial state. */
+int bsw_cfl_dt(bsw_disc disc, const bsw_params* prm, const void* W, double cfl, double* dt_out);
 
 /* ---------------------------------------------------------------- whole solve */
 /* Backward-Euler time loop from the state in W (device, updated in place) to
- * opts->t_end: per step b_old, then Newton (residual, linearize, block-Jacobi
- * GMRES for Eq. Newton, backtracking on ||R||, update) until
+ * opts->t_end: per step b_old, then inexact Newton (residual, linearize,
+ * block-Jacobi GMRES for Eq. Newton, backtracking on ||R||, update) until
  * ||dW||_inf <= newton_tol (1 + ||W||_inf) or max_newton iterations.
  * Returns BSW_W_NOT_CONVERGED if any step hit the cap. */
 int bsw_solve(bsw_disc disc, const bsw_params* prm, const bsw_solve_opts* opts, void* W,

@@ -147,7 +147,7 @@ class SolveOptions:
     max_newton: int = 10
     gmres_m: int = 30
     gmres_max_restarts: int = 40
-    newton_tol: float = 1e-12
+    newton_tol: float = 1e-10
     gmres_rtol: float = 1e-12
     cfl: float = 0.2
     t_end: float = 1.0

@@ -1227,14 +1227,16 @@ int or_solve(void* h, const or_params* p, const or_solve_opts* o, double* W, or_
   double diag[4];
   memset(st, 0, sizeof(*st));
   double dt = o->dt_override > 0 ? o->dt_override : or_cfl_dt(h, p, W, o->cfl);
-  int nsteps = (int)ceil(o->t_end / dt - 1e-12);
+  double nt = ceil(o->t_end / dt - 1e-12);
+  if (!(nt <= 2.0e9)) return -1;
+  int nsteps = (int)nt;
   if (nsteps < 1) nsteps = 1;
   if (o->max_steps >= 0 && nsteps > o->max_steps) nsteps = o->max_steps;
   or_diagnostics(h, p, W, diag);
   st->mass0 = diag[0]; st->dt = dt;
   double t = 0.0;
   for (int k = 1; k <= nsteps; ++k) {
-    double dtk = (k < (int)ceil(o->t_end / dt - 1e-12)) ? dt : o->t_end - (k - 1) * dt;
+    double dtk = (k < (int)nt) ? dt : o->t_end - (k - 1) * dt;
     or_step_begin(h, p, dtk, W, bold);
     int conv, gits;
     int its = or_newton_step(h, p, dtk, W, bold, o, &conv, &gits);

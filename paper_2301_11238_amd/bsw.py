@@ -71,6 +71,7 @@ SIGNATURES = {
     "bsw_stage_update": (C.c_int, [_VP, C.POINTER(Params), _VP, _VP, C.c_double, _DP]),
     "bsw_diagnostics": (C.c_int, [_VP, C.POINTER(Params), _VP, _DP]),
     "bsw_norm2": (C.c_int, [_VP, _VP, _DP]),
+    "bsw_cfl_dt": (C.c_int, [_VP, C.POINTER(Params), _VP, C.c_double, _DP]),
     "bsw_solve": (C.c_int, [_VP, C.POINTER(Params), C.POINTER(SolveOpts), _VP, C.POINTER(SolveStats)]),
 }
 
@@ -121,8 +122,8 @@ class Options:
     max_newton: int = 10
     gmres_m: int = 30
     gmres_max_iters: int = 1200
-    newton_tol: float = 1e-12
-    gmres_rtol: float = 1e-12
+    newton_tol: float = 1e-10
+    gmres_rtol: float = 1e-10
     cfl: float = 0.2
     t_end: float = 1.0
     dt: float = 0.0
@@ -284,6 +285,11 @@ class Disc:
     def norm2(self, x) -> float:
         out = C.c_double(0.0)
         self._ck(lib().bsw_norm2(self.h, _ptr(x), C.byref(out)))
+        return out.value
+
+    def cfl_dt(self, params: Params, W, cfl: float) -> float:
+        out = C.c_double(0.0)
+        self._ck(lib().bsw_cfl_dt(self.h, C.byref(params), _ptr(W), float(cfl), C.byref(out)))
         return out.value
 
     def solve(self, params: Params, opts: Options, W):

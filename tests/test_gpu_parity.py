@@ -197,3 +197,10 @@ def test_errors_are_reported(ctx):
         pr.disc.operator_apply(bad, 0.01, W, W[:3].contiguous())
     with pytest.raises(bsw.BswError):
         bsw.Disc(pr.mesh, 5)
+    # a step count beyond 2e9 is refused instead of overflowing
+    with pytest.raises(bsw.BswError):
+        pr.disc.solve(cp, bsw.Options(t_end=1e12, dt=1e-3, max_steps=1), W)
+    # max_steps bounds a long horizon; every step uses the fixed dt
+    Wc = pr.dev(pr.orc.project_ic(wl.IC(kind=wl.IC_CONST, a=1.0)))
+    st = pr.disc.solve(cp, bsw.Options(t_end=1e5, dt=1e-3, max_steps=2), Wc)
+    assert st["steps"] == 2 and st["t_end"] == pytest.approx(2e-3)
