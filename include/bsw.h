@@ -154,14 +154,14 @@ int bsw_operator_apply(bsw_disc disc, const bsw_params* prm, double dt, const vo
 /* ---------------------------------------------------------------- element-block Jacobian (Appendix A) */
 /* Records W (device pointer, kept by reference: the caller must not change or
  * free it until the next linearize), the parameters and dt; assembles the
- * diagonal blocks dR_e/dW_e of Eq. Newton and LU-factors them (partial
+ * diagonal blocks dR_e/dW_e of Eq. Newton and inverts them (LU with partial
  * pivoting) for the block-Jacobi preconditioner. */
 int bsw_jacobian_linearize(bsw_disc disc, const bsw_params* prm, double dt, const void* W);
 /* y = (dR/dW)(W) x, the exact directional derivative including the HLL wave
  * speeds and the face coupling to neighbours (matrix-free).  BSW_E_STATE
  * before the first linearize. */
 int bsw_jacobian_apply(bsw_disc disc, const void* x, void* y);
-/* y = blockdiag(dR_e/dW_e)^{-1} x using the factors of the last linearize. */
+/* y = blockdiag(dR_e/dW_e)^{-1} x using the inverses of the last linearize. */
 int bsw_precond_apply(bsw_disc disc, const void* x, void* y);
 /* Writes the unfactored diagonal blocks of the last linearize to blocks
  * (device, [n_el][bs][bs] row-major, bs = n_f n_p, row/column index f*n_p+i). */

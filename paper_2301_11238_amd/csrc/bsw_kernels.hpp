@@ -279,70 +279,176 @@ __global__ void __launch_bounds__(256) k_step_begin(const T* __restrict__ W, T* 
     for (int i = 0; i < S::NP; ++i) bold[(size_t)(f * S::NP + i) * n + e] = acc[f][i];
 }
 
-// R = residual of Eq. WeakForm7 (element-centric; each element evaluates the
-// numerical fluxes on its own faces from its own and its neighbour's traces).
-template <int D, int P, class T>
-__global__ void __launch_bounds__(256) k_operator(const T* __restrict__ W, const T* __restrict__ bold,
-                                                   T* __restrict__ R, MeshView<T> m, DevParams<T> p) {
+// ------------------------------------------------------------------ blocked kernels
+// A workgroup takes EB consecutive elements.  Their coefficients are staged in
+// LDS with one coalesced pass; then one lane per (element, quadrature point)
+// and per (element, face point) evaluates the pointwise integrand and parks it
+// in LDS; then one lane per (element, output row) contracts it with the test
+// functions and writes the row.  This keeps every lane's live state to one
+// point (no register spills at P3 in FP64) and gives NQ + NFC*NFQ lanes per
+// element instead of one.
+template <int D, int P>
+struct Blk {
   using S = Shape<D, P>;
+  static constexpr int NFP = S::NFC * S::NFQ;                          // face points per element
+  static constexpr int NPT = S::NQ + NFP;                              // point items per element
+  static constexpr int EB = 256 / NPT;                                 // elements per workgroup
+  static constexpr int OA = 0;                                         // A[f]
+  static constexpr int OB = 1 + D;                                     // B[r][f]
+  static constexpr int OCE = OB + D * (1 + D);                         // CE[c]
+  static constexpr int OCB = OCE + D * D;                              // CB[r][c]
+  static constexpr int NVF = OCB + D * D * D;                          // reals per volume point
+  static constexpr int NFF = 1 + D + D * D;                            // reals per face point
+};
+
+// MODE 0: residual (x unused, bold subtracted); MODE 1: Jacobian product
+// along x (bold unused).
+template <int D, int P, class T, int MODE>
+__global__ void __launch_bounds__(256) k_elem_blocked(const T* __restrict__ W, const T* __restrict__ x,
+                                                       const T* __restrict__ bold, T* __restrict__ out,
+                                                       MeshView<T> m, DevParams<T> p) {
+  using S = Shape<D, P>;
+  using B = Blk<D, P>;
+  constexpr bool TAN = MODE == 1;
   const Tab<D, P, T>& tb = tab<D, P, T>();
   const int n = m.n_el;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  T w[S::NF][S::NP];
-  load_coeffs<D, P, T>(W, n, e, w);
-  Geo<D, T> g;
-  load_geo<D, T>(m, e, g);
-  T acc[S::NF][S::NP];
-#pragma unroll
-  for (int f = 0; f < S::NF; ++f)
-#pragma unroll
-    for (int i = 0; i < S::NP; ++i) acc[f][i] = T(0);
-#pragma unroll 1
-  for (int q = 0; q < S::NQ; ++q) {
-    T X[S::NF];
-    interp<D, P, T>(tb.phi[q], w, X);
-    Pt<D, T> s;
-    unpack<D, T>(X, s);
-    Stress<D, T> st;
-    stress<D, T>(p, s.E, st);
-    T A[1 + D], B[D][1 + D], CE[D * D], CB[D][D * D];
-    volume_integrand<D, T>(p, g, tb.qw[q] * g.detJ, s, st, A, B, CE, CB);
-    contract_volume<D, P, T>(tb, q, A, B, CE, CB, acc);
+  const int tid = threadIdx.x;
+  const int e0 = blockIdx.x * B::EB;
+  __shared__ T sW[S::BS][B::EB];
+  __shared__ T sX[TAN ? S::BS : 1][TAN ? B::EB : 1];
+  __shared__ T sV[S::NQ][B::NVF][B::EB];
+  __shared__ T sF[B::NFP][B::NFF][B::EB];
+
+  for (int idx = tid; idx < S::BS * B::EB; idx += 256) {
+    const int row = idx / B::EB, el = idx % B::EB, e = e0 + el;
+    sW[row][el] = e < n ? W[(size_t)row * n + e] : T(0);
+    if constexpr (TAN) sX[row][el] = e < n ? x[(size_t)row * n + e] : T(0);
   }
+  __syncthreads();
+
+  if (tid < B::EB * B::NPT) {
+    const int el = tid % B::EB, k = tid / B::EB, e = e0 + el;
+    if (e < n) {
+      if (k < S::NQ) {
+        const int q = k;
+        Geo<D, T> g;
+        load_geo<D, T>(m, e, g);
+        T X[S::NF];
 #pragma unroll
-  for (int f = 0; f < S::NV; ++f)
+        for (int f = 0; f < S::NF; ++f) {
+          T s = T(0);
 #pragma unroll
-    for (int i = 0; i < S::NP; ++i) acc[f][i] -= bold[(size_t)(f * S::NP + i) * n + e];
-#pragma unroll 1
-  for (int fc = 0; fc < S::NFC; ++fc) {
-    const int code = m.nbr[(size_t)fc * n + e];
-    T nv[D];
+          for (int i = 0; i < S::NP; ++i) s += tb.phi[q][i] * sW[f * S::NP + i][el];
+          X[f] = s;
+        }
+        Pt<D, T> s;
+        unpack<D, T>(X, s);
+        Stress<D, T> st;
+        stress<D, T>(p, s.E, st);
+        T A[1 + D], Bm[D][1 + D], CE[D * D], CB[D][D * D];
+        const T wq = tb.qw[q] * g.detJ;
+        if constexpr (TAN) {
+          T dX[S::NF];
 #pragma unroll
-    for (int a = 0; a < D; ++a) nv[a] = m.nrm[(size_t)(fc * D + a) * n + e];
-    const T hl = m.hlen[(size_t)fc * n + e];
-#pragma unroll 1
-    for (int rr = 0; rr < S::NFQ; ++rr) {
-      T Xm[S::NF];
-      interp<D, P, T>(tb.fphi[fc][rr], w, Xm);
-      Pt<D, T> sm, sp;
-      unpack<D, T>(Xm, sm);
-      if (code >= 0) {
-        T Xp[S::NF];
-        interp_global<D, P, T>(tb, code & 3, S::NFQ - 1 - rr, W, n, code >> 2, Xp);
-        unpack<D, T>(Xp, sp);
+          for (int f = 0; f < S::NF; ++f) {
+            T s2 = T(0);
+#pragma unroll
+            for (int i = 0; i < S::NP; ++i) s2 += tb.phi[q][i] * sX[f * S::NP + i][el];
+            dX[f] = s2;
+          }
+          Pt<D, T> ds;
+          unpack<D, T>(dX, ds);
+          volume_integrand_tan<D, T>(p, g, wq, s, st, ds, A, Bm, CE, CB);
+        } else {
+          volume_integrand<D, T>(p, g, wq, s, st, A, Bm, CE, CB);
+        }
+#pragma unroll
+        for (int f = 0; f <= D; ++f) sV[q][B::OA + f][el] = A[f];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+          for (int f = 0; f <= D; ++f) sV[q][B::OB + r * (1 + D) + f][el] = Bm[r][f];
+#pragma unroll
+        for (int c = 0; c < D * D; ++c) sV[q][B::OCE + c][el] = CE[c];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+          for (int c = 0; c < D * D; ++c) sV[q][B::OCB + r * D * D + c][el] = CB[r][c];
       } else {
-        exterior<D, T>(p, nv, sm, sp);
+        const int kp = k - S::NQ, fc = kp / S::NFQ, rr = kp % S::NFQ;
+        const int code = m.nbr[(size_t)fc * n + e];
+        T nv[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) nv[a] = m.nrm[(size_t)(fc * D + a) * n + e];
+        const T wr = tb.fw[rr] * m.hlen[(size_t)fc * n + e];
+        T Xm[S::NF], dXm[S::NF];
+#pragma unroll
+        for (int f = 0; f < S::NF; ++f) {
+          T s1 = T(0), s2 = T(0);
+#pragma unroll
+          for (int i = 0; i < S::NP; ++i) {
+            s1 += tb.fphi[fc][rr][i] * sW[f * S::NP + i][el];
+            if constexpr (TAN) s2 += tb.fphi[fc][rr][i] * sX[f * S::NP + i][el];
+          }
+          Xm[f] = s1;
+          dXm[f] = s2;
+        }
+        Pt<D, T> sm, sp, dsm, dsp;
+        unpack<D, T>(Xm, sm);
+        if constexpr (TAN) unpack<D, T>(dXm, dsm);
+        if (code >= 0) {
+          T Xp[S::NF];
+          interp_global<D, P, T>(tb, code & 3, S::NFQ - 1 - rr, W, n, code >> 2, Xp);
+          unpack<D, T>(Xp, sp);
+          if constexpr (TAN) {
+            T dXp[S::NF];
+            interp_global<D, P, T>(tb, code & 3, S::NFQ - 1 - rr, x, n, code >> 2, dXp);
+            unpack<D, T>(dXp, dsp);
+          }
+        } else {
+          exterior<D, T>(p, nv, sm, sp);
+          if constexpr (TAN) exterior_tan<D, T>(p, nv, dsm, dsp);
+        }
+        T FV[1 + D], FE[D * D];
+        if constexpr (TAN) face_flux_tan<D, T>(p, nv, wr, sm, sp, dsm, dsp, FV, FE);
+        else face_flux<D, T>(p, nv, wr, sm, sp, FV, FE);
+#pragma unroll
+        for (int f = 0; f <= D; ++f) sF[kp][f][el] = FV[f];
+#pragma unroll
+        for (int c = 0; c < D * D; ++c) sF[kp][1 + D + c][el] = FE[c];
       }
-      T FV[1 + D], FE[D * D];
-      face_flux<D, T>(p, nv, tb.fw[rr] * hl, sm, sp, FV, FE);
-      lift_face<D, P, T>(tb, fc, rr, FV, FE, acc);
     }
   }
+  __syncthreads();
+
+  for (int idx = tid; idx < S::BS * B::EB; idx += 256) {
+    const int row = idx / B::EB, el = idx % B::EB, e = e0 + el;
+    if (e >= n) continue;
+    const int f = row / S::NP, i = row % S::NP;
+    T acc = T(0);
+    if (f <= D) {
 #pragma unroll
-  for (int f = 0; f < S::NF; ++f)
+      for (int q = 0; q < S::NQ; ++q) {
+        acc += tb.phi[q][i] * sV[q][B::OA + f][el];
 #pragma unroll
-    for (int i = 0; i < S::NP; ++i) R[(size_t)(f * S::NP + i) * n + e] = acc[f][i];
+        for (int r = 0; r < D; ++r) acc += tb.dphi[q][i][r] * sV[q][B::OB + r * (1 + D) + f][el];
+      }
+#pragma unroll
+      for (int kp = 0; kp < B::NFP; ++kp) acc += tb.fphi[kp / S::NFQ][kp % S::NFQ][i] * sF[kp][f][el];
+      if constexpr (!TAN) acc -= bold[(size_t)row * n + e];
+    } else {
+      const int c = f - (1 + D);
+#pragma unroll
+      for (int q = 0; q < S::NQ; ++q) {
+        acc += tb.phi[q][i] * sV[q][B::OCE + c][el];
+#pragma unroll
+        for (int r = 0; r < D; ++r) acc += tb.dphi[q][i][r] * sV[q][B::OCB + r * D * D + c][el];
+      }
+#pragma unroll
+      for (int kp = 0; kp < B::NFP; ++kp) acc += tb.fphi[kp / S::NFQ][kp % S::NFQ][i] * sF[kp][1 + D + c][el];
+    }
+    out[(size_t)row * n + e] = acc;
+  }
 }
 
 // Tangent of the element residual.  The perturbation is either a full vector
@@ -430,91 +536,125 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
   }
 }
 
+// Diagonal block of element e = blockIdx.x, one lane per column, written
+// element-major and row-major: blocks[(e * BS + row) * BS + col] (coalesced
+// across the columns of a row).
 template <int D, int P, class T>
-__global__ void __launch_bounds__(256) k_jac_apply(const T* __restrict__ W, const T* __restrict__ x, T* __restrict__ y,
-                                                    MeshView<T> m, DevParams<T> p) {
-  using S = Shape<D, P>;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m.n_el) return;
-  T acc[S::NF][S::NP];
-  elem_tangent<D, P, T, false>(tab<D, P, T>(), W, x, m, p, e, 0, acc);
-#pragma unroll
-  for (int f = 0; f < S::NF; ++f)
-#pragma unroll
-    for (int i = 0; i < S::NP; ++i) y[(size_t)(f * S::NP + i) * m.n_el + e] = acc[f][i];
-}
-
-// Column `col` of every diagonal block: blocks[(row * BS + col) * n_el + e].
-template <int D, int P, class T>
-__global__ void __launch_bounds__(256) k_jac_columns(const T* __restrict__ W, T* __restrict__ blocks, MeshView<T> m,
+__global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, T* __restrict__ blocks, MeshView<T> m,
                                                       DevParams<T> p) {
   using S = Shape<D, P>;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int col = blockIdx.y;
-  if (e >= m.n_el) return;
+  const int e = blockIdx.x;
+  const int col = threadIdx.x;
+  if (col >= S::BS) return;
   T acc[S::NF][S::NP];
   elem_tangent<D, P, T, true>(tab<D, P, T>(), W, nullptr, m, p, e, col, acc);
+  T* blk = blocks + (size_t)e * S::BS * S::BS;
 #pragma unroll
   for (int f = 0; f < S::NF; ++f)
 #pragma unroll
-    for (int i = 0; i < S::NP; ++i) blocks[((size_t)(f * S::NP + i) * S::BS + col) * m.n_el + e] = acc[f][i];
+    for (int i = 0; i < S::NP; ++i) blk[(f * S::NP + i) * S::BS + col] = acc[f][i];
 }
 
-// In-place LU with partial pivoting of every block ([BS][BS][n_el] layout);
-// perm[k][e] = original row of factor row k.  One lane per element.
+// Inverse of one diagonal block per workgroup (one wavefront): LU with
+// partial pivoting staged in LDS (lanes own rows for the pivot search and the
+// elimination), then lane k solves L U y = P e_k for column k of the inverse.
+// The inverse is written element-fastest, Ainv[(row * BS + col) * n + e], so
+// the preconditioner apply is a coalesced batched mat-vec.
 template <int BS, class T>
-__global__ void __launch_bounds__(256) k_block_lu(T* __restrict__ A, int* __restrict__ perm, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  auto a = [&](int r, int c) -> T& { return A[((size_t)r * BS + c) * n + e]; };
-  for (int k = 0; k < BS; ++k) perm[(size_t)k * n + e] = k;
+__global__ void __launch_bounds__(64) k_block_inverse(const T* __restrict__ A, T* __restrict__ Ainv, int n) {
+  constexpr int LD = BS + 1;
+  constexpr int RPL = (BS + 63) / 64;  // rows per lane
+  __shared__ T a[BS * LD];
+  __shared__ int pr[BS];
+  __shared__ int piv_s;
+  const int e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const T* src = A + (size_t)e * BS * BS;
+  for (int idx = lane; idx < BS * BS; idx += 64) a[(idx / BS) * LD + idx % BS] = src[idx];
+  for (int r = lane; r < BS; r += 64) pr[r] = r;
+  __syncthreads();
   for (int k = 0; k < BS; ++k) {
-    int pv = k;
-    T big = fabs(a(k, k));
-    for (int r = k + 1; r < BS; ++r) {
-      const T v = fabs(a(r, k));
-      if (v > big) { big = v; pv = r; }
+    // pivot: largest |a[i][k]|, i >= k (lowest index on ties)
+    T best = T(-1);
+    int bi = k;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = lane + 64 * t;
+      if (i >= k && i < BS) {
+        const T v = fabs(a[i * LD + k]);
+        if (v > best) { best = v; bi = i; }
+      }
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const T ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) piv_s = bi;
+    __syncthreads();
+    const int pv = piv_s;
     if (pv != k) {
-      for (int c = 0; c < BS; ++c) { const T t = a(k, c); a(k, c) = a(pv, c); a(pv, c) = t; }
-      const int t = perm[(size_t)k * n + e];
-      perm[(size_t)k * n + e] = perm[(size_t)pv * n + e];
-      perm[(size_t)pv * n + e] = t;
+      for (int j = lane; j < BS; j += 64) {
+        const T t = a[k * LD + j];
+        a[k * LD + j] = a[pv * LD + j];
+        a[pv * LD + j] = t;
+      }
+      if (lane == 0) {
+        const int t = pr[k];
+        pr[k] = pr[pv];
+        pr[pv] = t;
+      }
     }
-    const T inv = T(1) / a(k, k);
-    for (int r = k + 1; r < BS; ++r) {
-      const T l = a(r, k) * inv;
-      a(r, k) = l;
-      for (int c = k + 1; c < BS; ++c) a(r, c) -= l * a(k, c);
+    __syncthreads();
+    const T inv = T(1) / a[k * LD + k];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = lane + 64 * t;
+      if (i > k && i < BS) {
+        const T l = a[i * LD + k] * inv;
+        a[i * LD + k] = l;
+        for (int j = k + 1; j < BS; ++j) a[i * LD + j] -= l * a[k * LD + j];
+      }
     }
+    __syncthreads();
+  }
+  // columns of the inverse: A^{-1} e_k = U^{-1} L^{-1} P e_k, (P e_k)[r] = [pr[r] == k]
+  for (int k = lane; k < BS; k += 64) {
+    T y[BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) y[r] = pr[r] == k ? T(1) : T(0);
+#pragma unroll
+    for (int r = 1; r < BS; ++r) {
+      T s = y[r];
+#pragma unroll
+      for (int c = 0; c < r; ++c) s -= a[r * LD + c] * y[c];
+      y[r] = s;
+    }
+#pragma unroll
+    for (int r = BS - 1; r >= 0; --r) {
+      T s = y[r];
+#pragma unroll
+      for (int c = r + 1; c < BS; ++c) s -= a[r * LD + c] * y[c];
+      y[r] = s / a[r * LD + r];
+    }
+#pragma unroll
+    for (int r = 0; r < BS; ++r) Ainv[((size_t)r * BS + k) * n + e] = y[r];
   }
 }
 
-// y = U^{-1} L^{-1} P x per element (x and y in the state layout).
+// y = blockdiag(A_e)^{-1} x: one lane per (row, element), element fastest.
 template <int BS, class T>
-__global__ void __launch_bounds__(256) k_block_solve(const T* __restrict__ LU, const int* __restrict__ perm,
-                                                      const T* __restrict__ x, T* __restrict__ y, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  T v[BS];
+__global__ void __launch_bounds__(256) k_block_apply(const T* __restrict__ Ainv, const T* __restrict__ x,
+                                                      T* __restrict__ y, int n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)BS * n) return;
+  const int row = (int)(idx / n), e = (int)(idx % n);
+  const T* arow = Ainv + (size_t)row * BS * n + e;
+  T s = T(0);
 #pragma unroll
-  for (int k = 0; k < BS; ++k) v[k] = x[(size_t)perm[(size_t)k * n + e] * n + e];
-#pragma unroll
-  for (int i = 1; i < BS; ++i) {
-    T s = v[i];
-#pragma unroll
-    for (int j = 0; j < i; ++j) s -= LU[((size_t)i * BS + j) * n + e] * v[j];
-    v[i] = s;
-  }
-#pragma unroll
-  for (int i = BS - 1; i >= 0; --i) {
-    T s = v[i];
-#pragma unroll
-    for (int j = i + 1; j < BS; ++j) s -= LU[((size_t)i * BS + j) * n + e] * v[j];
-    v[i] = s / LU[((size_t)i * BS + i) * n + e];
-  }
-#pragma unroll
-  for (int k = 0; k < BS; ++k) y[(size_t)k * n + e] = v[k];
+  for (int j = 0; j < BS; ++j) s += arow[(size_t)j * n] * x[(size_t)j * n + e];
+  y[(size_t)row * n + e] = s;
 }
 
 }  // namespace bsw

@@ -60,14 +60,14 @@ struct bsw_disc_s {
   const void* lin_W = nullptr;
   bsw_params lin_prm{};
   double lin_dt = 0.0;
-  void* blocks = nullptr;  // factored [bs][bs][n_el]
-  void* blocks_raw = nullptr;  // unfactored copy (kept for inspection)
-  int* perm = nullptr;
+  void* blocks = nullptr;      // block inverses, [row][col][n_el]
+  void* blocks_raw = nullptr;  // unfactored blocks, [n_el][row][col]
   // reduction scratch
   double* part = nullptr;
   size_t part_len = 0;
   double* red_out = nullptr;      // device [64]
-  double* red_host = nullptr;     // pinned [64]
+  double* red_host = nullptr;     // pinned, device-mapped [80]
+  double* red_dev_map = nullptr;  // device view of red_host
   // solver workspace
   void* gm = nullptr;             // GMRES Krylov basis and vectors
   size_t gm_bytes = 0;
@@ -219,12 +219,13 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce_final(const double* __re
   if (threadIdx.x == 0) out[v] = sh[0];
 }
 
-// dot products of w with k vectors V[j] (stride ld) -> part[j][blk]
+// dot products of w with k vectors V[j] (stride ld) -> part[j][blk]; a grid
+// row y == k (when present) gives w . w
 template <class T>
 __global__ void __launch_bounds__(kRedThreads) k_multidot(const T* __restrict__ V, size_t ld, const T* __restrict__ w,
-                                                           int64_t n, double* __restrict__ part) {
+                                                           int64_t n, int k, double* __restrict__ part) {
   const int j = blockIdx.y;
-  const T* v = V + (size_t)j * ld;
+  const T* v = j < k ? V + (size_t)j * ld : w;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
     acc += (double)v[i] * (double)w[i];
@@ -264,6 +265,17 @@ __global__ void __launch_bounds__(256) k_multi_axpy(T* __restrict__ w, const T* 
   double s = 0.0;
   for (int j = 0; j < k; ++j) s += h.h[j] * (double)V[(size_t)j * ld + i];
   w[i] = (T)((double)w[i] + sgn * s);
+}
+
+// y = s * (w - sum_j h[j] V[j])
+template <class T>
+__global__ void __launch_bounds__(256) k_axpy_scale(const T* __restrict__ w, const T* __restrict__ V, size_t ld, int k,
+                                                     Coef h, double s, T* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = (double)w[i];
+  for (int j = 0; j < k; ++j) acc -= h.h[j] * (double)V[(size_t)j * ld + i];
+  y[i] = (T)(acc * s);
 }
 
 template <class T>
@@ -417,17 +429,6 @@ __global__ void __launch_bounds__(256) k_project_ic(T* __restrict__ W, MeshView<
     for (int i = 0; i < S::NP; ++i) W[(size_t)(f * S::NP + i) * n + e] = f <= D ? (T)acc[f][i] : T(0);
 }
 
-// raw (unfactored) blocks [bs][bs][n] -> row-major per element [n][bs][bs]
-template <class T>
-__global__ void __launch_bounds__(256) k_blocks_export(const T* __restrict__ A, T* __restrict__ out, int bs, int n) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = (int64_t)bs * bs * n;
-  if (idx >= tot) return;
-  const int e = (int)(idx % n);
-  const int64_t rc = idx / n;
-  out[(size_t)e * bs * bs + rc] = A[idx];
-}
-
 // ---------------------------------------------------------------- reductions (host helpers)
 int ensure_part(bsw_disc d, size_t len) {
   if (d->part_len >= len) return BSW_OK;
@@ -460,8 +461,9 @@ struct OpLaunch {
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
-    hipLaunchKernelGGL((k_operator<D, P, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream, (const T*)W,
-                       (const T*)bold, (T*)R, m, devparams<T>(*p, dt));
+    hipLaunchKernelGGL((k_elem_blocked<D, P, T, 0>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0,
+                       d->mesh->ctx->stream, (const T*)W, (const T*)nullptr, (const T*)bold, (T*)R, m,
+                       devparams<T>(*p, dt));
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -484,8 +486,9 @@ struct JacApplyLaunch {
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
-    hipLaunchKernelGGL((k_jac_apply<D, P, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream,
-                       (const T*)d->lin_W, (const T*)x, (T*)y, m, devparams<T>(d->lin_prm, d->lin_dt));
+    hipLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0,
+                       d->mesh->ctx->stream, (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, m,
+                       devparams<T>(d->lin_prm, d->lin_dt));
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -498,14 +501,12 @@ struct LinearizeLaunch {
     using S = Shape<D, P>;
     auto m = view<T>(d);
     bsw_ctx c = d->mesh->ctx;
-    dim3 gcols((unsigned)((m.n_el + 255) / 256), (unsigned)S::BS);
-    hipLaunchKernelGGL((k_jac_columns<D, P, T>), gcols, dim3(256), 0, c->stream, (const T*)d->lin_W,
+    const int tpb = S::BS <= 64 ? 64 : 128;
+    hipLaunchKernelGGL((k_jac_columns<D, P, T>), dim3(m.n_el), dim3(tpb), 0, c->stream, (const T*)d->lin_W,
                        (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt));
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(d->blocks, d->blocks_raw, sizeof(T) * (size_t)S::BS * S::BS * m.n_el,
-                             hipMemcpyDeviceToDevice, c->stream));
-    hipLaunchKernelGGL((k_block_lu<S::BS, T>), grid1(m.n_el), dim3(256), 0, c->stream, (T*)d->blocks, d->perm,
-                       m.n_el);
+    hipLaunchKernelGGL((k_block_inverse<S::BS, T>), dim3(m.n_el), dim3(64), 0, c->stream,
+                       (const T*)d->blocks_raw, (T*)d->blocks, m.n_el);
     HIPCHK(c, hipGetLastError());
     return BSW_OK;
   }
@@ -517,8 +518,8 @@ struct PrecLaunch {
   int operator()() {
     using S = Shape<D, P>;
     auto m = view<T>(d);
-    hipLaunchKernelGGL((k_block_solve<S::BS, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream,
-                       (const T*)d->blocks, d->perm, (const T*)x, (T*)y, m.n_el);
+    hipLaunchKernelGGL((k_block_apply<S::BS, T>), grid1((int64_t)S::BS * m.n_el), dim3(256), 0,
+                       d->mesh->ctx->stream, (const T*)d->blocks, (const T*)x, (T*)y, m.n_el);
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -593,29 +594,25 @@ struct Solver {
   double* hdev = nullptr;
   double hh[80];
 
-  int dots(int k, const T* x, double* host_out) {
+  // host_out[0..k) = V[j] . x, and host_out[k] = x . x when self_dot
+  int dots(int k, const T* x, bool self_dot, double* host_out) {
     bsw_ctx c = d->mesh->ctx;
     const int nblk = red_blocks(n);
-    if (int rc = ensure_part(d, (size_t)nblk * (k + 1))) return rc;
-    hipLaunchKernelGGL((k_multidot<T>), dim3(nblk, k), dim3(kRedThreads), 0, c->stream, V, (size_t)n, x, n, d->part);
+    const int rows = k + (self_dot ? 1 : 0);
+    if (int rc = ensure_part(d, (size_t)nblk * rows)) return rc;
+    hipLaunchKernelGGL((k_multidot<T>), dim3(nblk, rows), dim3(kRedThreads), 0, c->stream, V, (size_t)n, x, n, k,
+                       d->part);
     HIPCHK(c, hipGetLastError());
-    hipLaunchKernelGGL(k_sum_rows, dim3(k), dim3(kRedThreads), 0, c->stream, d->part, nblk, hdev);
+    hipLaunchKernelGGL(k_sum_rows, dim3(rows), dim3(kRedThreads), 0, c->stream, d->part, nblk, d->red_dev_map);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(d->red_host, hdev, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int j = 0; j < k; ++j) host_out[j] = d->red_host[j];
+    for (int j = 0; j < rows; ++j) host_out[j] = ((volatile double*)d->red_host)[j];
     return BSW_OK;
   }
   int norm(const T* x, double* out) {
-    bsw_ctx c = d->mesh->ctx;
-    const int nblk = red_blocks(n);
-    if (int rc = ensure_part(d, (size_t)nblk)) return rc;
-    hipLaunchKernelGGL((k_multidot<T>), dim3(nblk, 1), dim3(kRedThreads), 0, c->stream, x, (size_t)n, x, n, d->part);
-    HIPCHK(c, hipGetLastError());
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kRedThreads), 0, c->stream, d->part, nblk, hdev);
-    HIPCHK(c, hipMemcpyAsync(d->red_host, hdev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    *out = std::sqrt(d->red_host[0]);
+    double v;
+    if (int rc = dots(0, x, true, &v)) return rc;
+    *out = std::sqrt(v);
     return BSW_OK;
   }
   int multi_axpy(T* y, int k, const double* hcoef, double sgn) {
@@ -653,18 +650,30 @@ struct Solver {
         JacApplyLaunch ja{d, z, w};
         if (int rc = dispatch(d, ja)) return rc;
         ++*iters;
+        // classical Gram-Schmidt twice; the second pass also returns w.w, so
+        // ||w - V h2||^2 = w.w - |h2|^2 (checked explicitly if that cancels)
         double h1[80], h2[80];
-        if (int rc = dots(j + 1, w, h1)) return rc;
+        if (int rc = dots(j + 1, w, false, h1)) return rc;
         if (int rc = multi_axpy(w, j + 1, h1, -1.0)) return rc;
-        if (int rc = dots(j + 1, w, h2)) return rc;
-        if (int rc = multi_axpy(w, j + 1, h2, -1.0)) return rc;
-        for (int i = 0; i <= j; ++i) H[i * M + j] = h1[i] + h2[i];
+        if (int rc = dots(j + 1, w, true, h2)) return rc;
+        double ww = h2[j + 1], hh = 0.0;
+        for (int i = 0; i <= j; ++i) { H[i * M + j] = h1[i] + h2[i]; hh += h2[i] * h2[i]; }
         double hn;
-        if (int rc = norm(w, &hn)) return rc;
+        Coef cf;
+        for (int i = 0; i < 65; ++i) cf.h[i] = i <= j ? h2[i] : 0.0;
+        if (hh <= 1e-4 * ww) {
+          hn = std::sqrt(std::max(ww - hh, 0.0));
+          if (hn > 0)
+            hipLaunchKernelGGL((k_axpy_scale<T>), grid1(n), dim3(256), 0, c->stream, w, V, (size_t)n, j + 1, cf,
+                               1.0 / hn, V + (size_t)(j + 1) * n, n);
+        } else {
+          if (int rc = multi_axpy(w, j + 1, h2, -1.0)) return rc;
+          if (int rc = norm(w, &hn)) return rc;
+          if (hn > 0)
+            hipLaunchKernelGGL((k_scale_copy<T>), grid1(n), dim3(256), 0, c->stream, w, V + (size_t)(j + 1) * n,
+                               1.0 / hn, n);
+        }
         H[(j + 1) * M + j] = hn;
-        if (hn > 0)
-          hipLaunchKernelGGL((k_scale_copy<T>), grid1(n), dim3(256), 0, c->stream, w, V + (size_t)(j + 1) * n,
-                             1.0 / hn, n);
         for (int i = 0; i < j; ++i) {
           const double t = cs[i] * H[i * M + j] + sn[i] * H[(i + 1) * M + j];
           H[(i + 1) * M + j] = -sn[i] * H[i * M + j] + cs[i] * H[(i + 1) * M + j];
@@ -871,8 +880,10 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
   }
   int rc = dev_alloc(c, &d->red_out, 64);
   if (!rc) rc = dev_alloc(c, &d->hcoef, 80);
-  if (!rc && hipHostMalloc((void**)&d->red_host, 80 * sizeof(double)) != hipSuccess)
+  if (!rc && hipHostMalloc((void**)&d->red_host, 80 * sizeof(double), hipHostMallocMapped) != hipSuccess)
     rc = fail(c, BSW_E_OOM, "hipHostMalloc");
+  if (!rc && hipHostGetDevicePointer((void**)&d->red_dev_map, d->red_host, 0) != hipSuccess)
+    rc = fail(c, BSW_E_HIP, "hipHostGetDevicePointer");
   if (rc) { bsw_disc_destroy(d); return rc; }
   *out = d;
   return BSW_OK;
@@ -880,7 +891,7 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
 
 int bsw_disc_destroy(bsw_disc d) {
   if (!d) return BSW_OK;
-  hfree(d->blocks); hfree(d->blocks_raw); hfree(d->perm); hfree(d->part); hfree(d->red_out);
+  hfree(d->blocks); hfree(d->blocks_raw); hfree(d->part); hfree(d->red_out);
   hfree(d->gm); hfree(d->hcoef);
   if (d->red_host) (void)hipHostFree(d->red_host);
   delete d;
@@ -930,8 +941,7 @@ int bsw_jacobian_linearize(bsw_disc d, const bsw_params* p, double dt, const voi
   bsw_ctx c = d->mesh->ctx;
   const size_t nb = (size_t)d->bs * d->bs * d->mesh->n_el;
   if (!d->blocks) {
-    if (hipMalloc(&d->blocks, nb * d->wsize) != hipSuccess || hipMalloc(&d->blocks_raw, nb * d->wsize) != hipSuccess ||
-        hipMalloc((void**)&d->perm, sizeof(int) * d->bs * d->mesh->n_el) != hipSuccess)
+    if (hipMalloc(&d->blocks, nb * d->wsize) != hipSuccess || hipMalloc(&d->blocks_raw, nb * d->wsize) != hipSuccess)
       return fail(c, BSW_E_OOM, "block-Jacobi storage");
   }
   d->lin_W = W;
@@ -961,14 +971,8 @@ int bsw_jacobian_blocks(bsw_disc d, void* blocks) {
   if (!d || !blocks) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
   if (!d->lin_W) return fail(d->mesh->ctx, BSW_E_STATE, "jacobian_blocks before jacobian_linearize");
   bsw_ctx c = d->mesh->ctx;
-  const int64_t tot = (int64_t)d->bs * d->bs * d->mesh->n_el;
-  if (d->precision == BSW_FP64)
-    hipLaunchKernelGGL((k_blocks_export<double>), grid1(tot), dim3(256), 0, c->stream, (const double*)d->blocks_raw,
-                       (double*)blocks, d->bs, (int)d->mesh->n_el);
-  else
-    hipLaunchKernelGGL((k_blocks_export<float>), grid1(tot), dim3(256), 0, c->stream, (const float*)d->blocks_raw,
-                       (float*)blocks, d->bs, (int)d->mesh->n_el);
-  HIPCHK(c, hipGetLastError());
+  const size_t bytes = (size_t)d->bs * d->bs * d->mesh->n_el * d->wsize;
+  HIPCHK(c, hipMemcpyAsync(blocks, d->blocks_raw, bytes, hipMemcpyDeviceToDevice, c->stream));
   return BSW_OK;
 }
 
@@ -1019,10 +1023,10 @@ int bsw_norm2(bsw_disc d, const void* x, double* out) {
   if (int rc = ensure_part(d, (size_t)nblk)) return rc;
   if (d->precision == BSW_FP64)
     hipLaunchKernelGGL((k_multidot<double>), dim3(nblk, 1), dim3(kRedThreads), 0, c->stream, (const double*)x,
-                       (size_t)n, (const double*)x, n, d->part);
+                       (size_t)n, (const double*)x, n, 0, d->part);
   else
     hipLaunchKernelGGL((k_multidot<float>), dim3(nblk, 1), dim3(kRedThreads), 0, c->stream, (const float*)x,
-                       (size_t)n, (const float*)x, n, d->part);
+                       (size_t)n, (const float*)x, n, 0, d->part);
   HIPCHK(c, hipGetLastError());
   const int ops[1] = {0};
   double s;
