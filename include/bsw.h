@@ -95,12 +95,15 @@ typedef struct {
                               [gmres_rtol, 1e-3] */
   double cfl, t_end, dt;
   int32_t max_steps;       /* < 0: all steps */
+  int32_t timing;          /* nonzero: time every Jacobian-apply launch with HIP events */
 } bsw_solve_opts;
 
 typedef struct {
   int32_t steps, newton_total, gmres_total, newton_max, capped, status;
   double dt, mass0, mass_end, max_mass_drift, active_pct, t_end, seconds;
   double operator_applies, jacobian_applies; /* counts of whole-mesh applies */
+  double jac_apply_seconds;  /* summed HIP-event time of the Jacobian-apply launches (timing != 0) */
+  double jac_apply_launches; /* launches that were timed */
 } bsw_solve_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -37,7 +37,7 @@ class IC(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("gmres_m", C.c_int32), ("gmres_max_iters", C.c_int32),
                 ("newton_tol", C.c_double), ("gmres_rtol", C.c_double), ("cfl", C.c_double),
-                ("t_end", C.c_double), ("dt", C.c_double), ("max_steps", C.c_int32)]
+                ("t_end", C.c_double), ("dt", C.c_double), ("max_steps", C.c_int32), ("timing", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -46,7 +46,8 @@ class SolveStats(C.Structure):
                 ("dt", C.c_double), ("mass0", C.c_double), ("mass_end", C.c_double),
                 ("max_mass_drift", C.c_double), ("active_pct", C.c_double), ("t_end", C.c_double),
                 ("seconds", C.c_double), ("operator_applies", C.c_double),
-                ("jacobian_applies", C.c_double)]
+                ("jacobian_applies", C.c_double), ("jac_apply_seconds", C.c_double),
+                ("jac_apply_launches", C.c_double)]
 
 
 # name -> (restype, argtypes); the exported symbols declared in include/bsw.h
@@ -128,6 +129,7 @@ class Options:
     t_end: float = 1.0
     dt: float = 0.0
     max_steps: int = -1
+    timing: int = 0
 
     def c(self) -> SolveOpts:
         o = SolveOpts()

@@ -279,6 +279,17 @@ __global__ void __launch_bounds__(256) k_step_begin(const T* __restrict__ W, T* 
     for (int i = 0; i < S::NP; ++i) bold[(size_t)(f * S::NP + i) * n + e] = acc[f][i];
 }
 
+// Workgroups are dealt round-robin to the chip's 8 XCDs, each with its own L2.
+// Map hardware workgroup b to element tile t so that every XCD gets one
+// contiguous run of tiles: face neighbours (adjacent elements and the
+// neighbouring row of a structured mesh) then mostly hit the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int q = nb / kXcd, r = nb % kXcd;
+  const int x = b % kXcd, k = b / kXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // ------------------------------------------------------------------ blocked kernels
 // A workgroup takes EB consecutive elements.  Their coefficients are staged in
 // LDS with one coalesced pass; then one lane per (element, quadrature point)
@@ -313,7 +324,7 @@ __global__ void __launch_bounds__(256) k_elem_blocked(const T* __restrict__ W, c
   const Tab<D, P, T>& tb = tab<D, P, T>();
   const int n = m.n_el;
   const int tid = threadIdx.x;
-  const int e0 = blockIdx.x * B::EB;
+  const int e0 = xcd_tile(blockIdx.x, gridDim.x) * B::EB;
   __shared__ T sW[S::BS][B::EB];
   __shared__ T sX[TAN ? S::BS : 1][TAN ? B::EB : 1];
   __shared__ T sV[S::NQ][B::NVF][B::EB];

@@ -1,6 +1,7 @@
 // Host side of the library: C ABI (include/bsw.h), mesh and discretisation
 // setup, kernel dispatch over (dimension, order, precision), deterministic
 // reductions, and the backward-Euler / Newton / block-Jacobi GMRES driver.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -483,12 +484,18 @@ struct StepBeginLaunch {
 
 struct JacApplyLaunch {
   bsw_disc d; const void* x; void* y;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional: timestamps of this dispatch
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
-    hipLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0,
-                       d->mesh->ctx->stream, (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, m,
-                       devparams<T>(d->lin_prm, d->lin_dt));
+    if (ev_start)
+      hipExtLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0,
+                            d->mesh->ctx->stream, ev_start, ev_stop, 0, (const T*)d->lin_W, (const T*)x,
+                            (const T*)nullptr, (T*)y, m, devparams<T>(d->lin_prm, d->lin_dt));
+    else
+      hipLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0,
+                         d->mesh->ctx->stream, (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, m,
+                         devparams<T>(d->lin_prm, d->lin_dt));
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -593,6 +600,29 @@ struct Solver {
   size_t m = 30;
   double* hdev = nullptr;
   double hh[80];
+  // optional HIP-event timing of the Jacobian-apply launches
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool ev_pending = false;
+  double jac_seconds = 0.0, jac_launches = 0.0;
+
+  int jac(const T* xin, T* yout) {
+    JacApplyLaunch ja{d, xin, yout};
+    if (timing) { ja.ev_start = ev0; ja.ev_stop = ev1; }
+    if (int rc = dispatch(d, ja)) return rc;
+    if (timing) ev_pending = true;
+    return BSW_OK;
+  }
+  // call after a stream synchronisation: the recorded pair has completed
+  void harvest() {
+    if (!ev_pending) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) {
+      jac_seconds += 1e-3 * ms;
+      jac_launches += 1;
+    }
+    ev_pending = false;
+  }
 
   // host_out[0..k) = V[j] . x, and host_out[k] = x . x when self_dot
   int dots(int k, const T* x, bool self_dot, double* host_out) {
@@ -606,6 +636,7 @@ struct Solver {
     hipLaunchKernelGGL(k_sum_rows, dim3(rows), dim3(kRedThreads), 0, c->stream, d->part, nblk, d->red_dev_map);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    harvest();
     for (int j = 0; j < rows; ++j) host_out[j] = ((volatile double*)d->red_host)[j];
     return BSW_OK;
   }
@@ -647,8 +678,7 @@ struct Solver {
       for (j = 0; j < M && *iters < max_iters; ++j) {
         PrecLaunch pl{d, V + (size_t)j * n, z};
         if (int rc = dispatch(d, pl)) return rc;
-        JacApplyLaunch ja{d, z, w};
-        if (int rc = dispatch(d, ja)) return rc;
+        if (int rc = jac(z, w)) return rc;
         ++*iters;
         // classical Gram-Schmidt twice; the second pass also returns w.w, so
         // ||w - V h2||^2 = w.w - |h2|^2 (checked explicitly if that cancels)
@@ -700,8 +730,7 @@ struct Solver {
       if (int rc = dispatch(d, pl)) return rc;
       hipLaunchKernelGGL((k_axpby<T>), grid1(n), dim3(256), 0, c->stream, x, 1.0, x, 1.0, w, n);
       // true residual r = b - J x -> V[0]
-      JacApplyLaunch ja{d, x, w};
-      if (int rc = dispatch(d, ja)) return rc;
+      if (int rc = jac(x, w)) return rc;
       hipLaunchKernelGGL((k_axpby<T>), grid1(n), dim3(256), 0, c->stream, V, 1.0, b, -1.0, w, n);
       if (int rc = norm(V, &beta)) return rc;
       *relres = beta / bn;
@@ -1074,6 +1103,18 @@ int solve_impl(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, b
   T* Wt = dW + n;
   T* bold = Wt + n;
   S.w = w; S.z = z;
+  S.timing = o->timing != 0;
+  if (S.timing) {
+    HIPCHK(c, hipEventCreate(&S.ev0));
+    HIPCHK(c, hipEventCreate(&S.ev1));
+  }
+  struct EvGuard {
+    Solver<T>* s;
+    ~EvGuard() {
+      if (s->ev0) (void)hipEventDestroy(s->ev0);
+      if (s->ev1) (void)hipEventDestroy(s->ev1);
+    }
+  } ev_guard{&S};
   auto t0 = std::chrono::steady_clock::now();
   std::memset(st, 0, sizeof(*st));
   double dg[4];
@@ -1160,6 +1201,8 @@ int solve_impl(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, b
   st->t_end = t;
   st->status = status;
   st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  st->jac_apply_seconds = S.jac_seconds;
+  st->jac_apply_launches = S.jac_launches;
   return status;
 }
 
