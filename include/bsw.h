@@ -73,6 +73,9 @@ typedef struct {
 } bsw_params;
 
 /* Analytic initial condition, L2-projected with the element rule; E = 0.
+ * Where the projected depth falls below a tenth of the element mean at a
+ * volume or face point (a discontinuous depth cut by the element), the higher
+ * depth modes are scaled so that the minimum is a tenth of the mean.
  * kinds: CONST h=a,u=(b,c); STEP_X h = x<x0 ? a : b; MOUND h = a+b exp(-|x-x0,y0|^2/d);
  * DISK h = |x-(x0,y0)|<r ? a : b; SINE_U h=a,u1=b sin(pi x/L); LINEAR_X h=a+b x;
  * SHEAR_Y h=a,u1=b cos(pi y/L); VORTEX h=a, u=b(sin(pi x/L)cos(pi y/L), -cos(pi x/L)sin(pi y/L)). */
@@ -85,6 +88,8 @@ typedef struct {
  * iterations per step).  dt > 0 fixes the step; otherwise
  * dt = cfl * h_min / max(|u| + sqrt(g h)) over the initial state's volume
  * points, and the last step is clipped to land on t_end. */
+/* With BSW_FP32 the tolerances are floored at newton_tol 2e-6 and gmres_rtol
+ * 1e-6 (float rounding of the state). */
 typedef struct {
   int32_t max_newton;      /* Newton iterations per time step */
   int32_t gmres_m;         /* GMRES restart length (<= 64) */

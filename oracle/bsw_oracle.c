@@ -1156,6 +1156,31 @@ static void ic_value(const or_ic* ic, int dim, const double* x, double* h, doubl
   }
 }
 
+/* Positivity reading for discontinuous initial depths: where the projected
+ * depth falls below a tenth of the element mean at a volume or face point, the
+ * non-constant depth modes are scaled so that the minimum becomes exactly a
+ * tenth of the mean (the mean, hence the mass, is unchanged). */
+static void ic_positivity(const or_ref* R, double* We) {
+  int np = R->np;
+  double mean = We[0] * R->phi[0][0];
+  double mn = 1e300;
+  for (int q = 0; q < R->nq; ++q) {
+    double s = 0.0;
+    for (int i = 0; i < np; ++i) s += R->phi[q][i] * We[i];
+    if (s < mn) mn = s;
+  }
+  for (int f = 0; f < R->nfc; ++f)
+    for (int r = 0; r < R->nfq; ++r) {
+      double s = 0.0;
+      for (int i = 0; i < np; ++i) s += R->fphi[f][r][i] * We[i];
+      if (s < mn) mn = s;
+    }
+  if (mean > 0.0 && mn < 0.1 * mean) {
+    double theta = 0.9 * mean / (mean - mn);
+    for (int i = 1; i < np; ++i) We[i] *= theta;
+  }
+}
+
 int or_project_ic(void* h, const or_ic* ic, double* W) {
   or_disc* D = h; or_ref* R = &D->ref; or_mesh* M = &D->mesh;
   int dim = R->dim, np = R->np, bs = R->nf * np;
@@ -1170,6 +1195,7 @@ int or_project_ic(void* h, const or_ic* ic, double* W) {
         for (int b = 0; b < dim; ++b) We[(1 + b) * np + i] += R->qw[q] * R->phi[q][i] * u[b];
       }
     }
+    ic_positivity(R, We);
   }
   return 0;
 }

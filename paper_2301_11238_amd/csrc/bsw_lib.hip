@@ -424,6 +424,28 @@ __global__ void __launch_bounds__(256) k_project_ic(T* __restrict__ W, MeshView<
       for (int f = 0; f <= D; ++f) acc[f][i] += c * val[f];
     }
   }
+  // positivity of the projected depth: where it drops below a tenth of the
+  // element mean at a volume or face point, scale the higher depth modes so
+  // the minimum is a tenth of the mean (mean and mass unchanged)
+  {
+    const double mean = acc[0][0] * (double)tb.phi[0][0];
+    double mn = INFINITY;
+    for (int q = 0; q < S::NQ; ++q) {
+      double s = 0.0;
+      for (int i = 0; i < S::NP; ++i) s += (double)tb.phi[q][i] * acc[0][i];
+      mn = fmin(mn, s);
+    }
+    for (int fc = 0; fc < S::NFC; ++fc)
+      for (int r = 0; r < S::NFQ; ++r) {
+        double s = 0.0;
+        for (int i = 0; i < S::NP; ++i) s += (double)tb.fphi[fc][r][i] * acc[0][i];
+        mn = fmin(mn, s);
+      }
+    if (mean > 0.0 && mn < 0.1 * mean) {
+      const double theta = 0.9 * mean / (mean - mn);
+      for (int i = 1; i < S::NP; ++i) acc[0][i] *= theta;
+    }
+  }
 #pragma unroll
   for (int f = 0; f < S::NF; ++f)
 #pragma unroll
@@ -1082,6 +1104,11 @@ int solve_impl(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, b
   bsw_ctx c = d->mesh->ctx;
   const int64_t n = bsw_state_len(d);
   const int M = std::max(1, std::min(64, o->gmres_m));
+  // FP32 state: Newton updates and Krylov residuals cannot go below a few
+  // units of float rounding, so the tolerances are floored there.
+  const double tol_floor = sizeof(T) == 4 ? 2e-6 : 0.0;
+  const double newton_tol = std::max(o->newton_tol, tol_floor);
+  const double gmres_rtol = std::max(o->gmres_rtol, sizeof(T) == 4 ? 1e-6 : 0.0);
   // workspace: V (M+1), w, z, R, Rt, rhs, dW, Wt, bold
   const size_t need = (size_t)(M + 1 + 8) * n * sizeof(T);
   if (d->gm_bytes < need) {
@@ -1151,7 +1178,7 @@ int solve_impl(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, b
         const double safe = 0.9 * eta * eta;
         eta = std::max(cand, safe > 0.1 ? safe : 0.0);
       }
-      eta = std::min(1e-3, std::max(eta, o->gmres_rtol));
+      eta = std::min(1e-3, std::max(eta, gmres_rtol));
       int gits = 0;
       double relres = 0.0;
       if (int rc = S.gmres(rhs, dW, eta, o->gmres_max_iters, &gits, &relres)) return rc;
@@ -1166,7 +1193,7 @@ int solve_impl(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, b
         const int ops[2] = {1, 1};
         if (int rc = finish(d, nblk, 2, ops, nm)) return rc;
       }
-      if (std::isfinite(nm[0]) && nm[0] <= o->newton_tol * (1.0 + nm[1])) {
+      if (std::isfinite(nm[0]) && nm[0] <= newton_tol * (1.0 + nm[1])) {
         hipLaunchKernelGGL((k_axpby<T>), grid1(n), dim3(256), 0, c->stream, W, 1.0, W, 1.0, dW, n);
         conv = 1;
         break;

@@ -40,7 +40,8 @@ def test_project_ic(ctx, dim, P, n):
     ics = [wl.IC(kind=wl.IC_STEP_X, a=1.0, b=0.1, x0=5.3),
            wl.IC(kind=wl.IC_MOUND, a=1.0, b=0.5, x0=10.0, y0=10.0, d=4.0)]
     if dim == 2:
-        ics += [wl.IC(kind=wl.IC_VORTEX, a=1.0, b=0.3, L=20.0), wl.IC(kind=wl.IC_LINEAR_X, a=3.0, b=-0.1)]
+        ics += [wl.IC(kind=wl.IC_VORTEX, a=1.0, b=0.3, L=20.0), wl.IC(kind=wl.IC_LINEAR_X, a=3.0, b=-0.1),
+                wl.IC(kind=wl.IC_DISK, a=2.0, b=0.5, x0=10.0, y0=10.0, r=2.5)]
     else:
         ics += [wl.IC(kind=wl.IC_SINE_U, a=1.0, b=0.3, L=10.0)]
     for ic in ics:
@@ -160,6 +161,8 @@ SOLVES = [
      wl.IC(kind=wl.IC_MOUND, a=1.0, b=0.5, x0=10.0, y0=10.0, d=4.0), 0.1),
     ("mound_2d_reg1_p3", 2, 3, 6, 1, 30.0, 0.5, 1e-2, 0.0,
      wl.IC(kind=wl.IC_MOUND, a=0.5, b=1.5, x0=10.0, y0=10.0, d=6.0), 0.25),
+    ("disk_2d_reg1_p3", 2, 3, 6, 1, 30.0, 0.5, 1e-2, 0.0,
+     wl.IC(kind=wl.IC_DISK, a=2.0, b=0.5, x0=10.0, y0=10.0, r=2.5), 0.25),
 ]
 
 

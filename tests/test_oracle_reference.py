@@ -148,3 +148,30 @@ def test_line_mesh(oracle_mod):
     assert abs(m["measure"] - 10.0) < 1e-14 and abs(m["hmin"] - 1.0) < 1e-14
     assert m["nbr"][0, 0] == -1 and m["nbr"][-1, 1] == -1
     assert all(m["nbr"][e, 1] == e + 1 and m["nbr_face"][e, 1] == 0 for e in range(9))
+
+
+@pytest.mark.parametrize("P", [2, 3])
+def test_disk_projection_positivity_reading(oracle_mod, P):
+    """Discontinuous disk depth: element means equal the element rule's
+    projection of the analytic depth; every volume and face point stays at or
+    above a tenth of its element mean, with equality where modes were scaled."""
+    xy, e2v = wl.mesh_tri(12, 20.0, 20.0, 0.1, 3)
+    o = oracle_mod.Oracle(2, P, xy, e2v)
+    ic = wl.IC(kind=wl.IC_DISK, a=2.0, b=0.5, x0=10.0, y0=10.0, r=2.5)
+    W = o.project_ic(ic)
+    t = o.ref_tables()
+    m = o.mesh_data()
+    x, y = m["xq"][:, :, 0], m["xq"][:, :, 1]
+    hq = np.where((x - 10) ** 2 + (y - 10) ** 2 < 2.5 ** 2, 2.0, 0.5)
+    c0 = np.einsum("q,q,eq->e", t["qw"], t["phi"][:, 0], hq)
+    assert np.abs(W[0, 0] - c0).max() < 1e-14
+    mean = W[0, 0] * t["phi"][0, 0]
+    hv = np.einsum("qi,ie->eq", t["phi"], W[0])
+    hf = np.einsum("fri,ie->efr", t["fphi"], W[0]).reshape(o.n_el, -1)
+    mn = np.minimum(hv.min(1), hf.min(1))
+    assert (mn >= 0.1 * mean - 1e-12).all()
+    hit = mn < 0.1 * mean + 1e-12
+    assert hit.any()   # the disk cuts elements whose projection had to be scaled
+    # elements not cut by the disk keep the plain projection (constant depth)
+    full = np.einsum("q,qi,eq->ie", t["qw"], t["phi"], hq)
+    assert np.abs(W[0][:, ~hit] - full[:, ~hit]).max() < 1e-14
