@@ -109,6 +109,7 @@ typedef struct {
   double operator_applies, jacobian_applies; /* counts of whole-mesh applies */
   double jac_apply_seconds;  /* summed HIP-event time of the Jacobian-apply launches (timing != 0) */
   double jac_apply_launches; /* launches that were timed */
+  double queue_seconds;      /* served solves: submit to admission (seconds is admission to completion) */
 } bsw_solve_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -199,6 +200,69 @@ int bsw_cfl_dt(bsw_disc disc, const bsw_params* prm, const void* W, double cfl, 
  * Returns BSW_W_NOT_CONVERGED if any step hit the cap. */
 int bsw_solve(bsw_disc disc, const bsw_params* prm, const bsw_solve_opts* opts, void* W,
               bsw_solve_stats* stats_out);
+
+/* ---------------------------------------------------------------- solve server (batched, continuous) */
+/* A server owns a worker thread, its own HIP stream on the context's device
+ * and a device-memory budget.  Submitted requests wait in a FIFO queue; between
+ * time steps the worker admits the queue head while its footprint
+ * (bsw_request_footprint) fits the remaining budget and fewer than max_slots
+ * solves are resident, and retires finished solves (state copied to host
+ * memory, device memory released).  Resident solves of the same order,
+ * precision and restart length form one batch: every stage of their time
+ * steps (b_old, residual, Jacobian blocks and inverses, block-Jacobi and
+ * matrix-free Jacobian applies, Krylov vector updates, reductions) is one
+ * kernel launch over all of them, while Newton, backtracking and GMRES
+ * decisions stay per solve.  Reductions are per solve with a fixed shape, so
+ * a solve's result does not depend on what else is resident.  Served solves
+ * are 2-D with P in 1..3; at most 128 per (order, precision, restart) batch.
+ * The algorithm per solve is that of bsw_solve. */
+typedef struct bsw_server_s* bsw_server;
+
+enum { BSW_REQ_QUEUED = 0, BSW_REQ_RUNNING = 1, BSW_REQ_DONE = 2, BSW_REQ_FAILED = 3, BSW_REQ_CANCELLED = 4 };
+
+/* One solve.  All pointers are HOST memory and are copied by
+ * bsw_solve_submit, so the caller may free them on return.  Mesh as for
+ * bsw_mesh_upload (dim = 2): xy[2 n_vert], el2vert[3 n_el].  W0 (optional)
+ * is an initial state of n_f n_p n_el reals of the request's precision in the
+ * SoA layout; when NULL the initial condition ic is projected. */
+typedef struct {
+  int64_t n_vert;
+  const double* xy;
+  int64_t n_el;
+  const int32_t* el2vert;
+  int32_t P;
+  int32_t precision;
+  bsw_params params;
+  bsw_ic ic;
+  const void* W0;
+  bsw_solve_opts opts;
+} bsw_solve_request;
+
+/* Device bytes a request occupies while resident: state and 11 + gmres_m
+ * work vectors, the diagonal Jacobian blocks and their inverses, reduction
+ * partials and mesh arrays.  -1 for an invalid request. */
+int64_t bsw_request_footprint(const bsw_solve_request* req);
+int bsw_server_create(bsw_ctx ctx, size_t hbm_budget_bytes, int max_slots, bsw_server* out);
+/* Stops the worker after its current step; unfinished requests are dropped. */
+int bsw_server_destroy(bsw_server server);
+/* Validates and copies the request; BSW_E_ARG if it is invalid or its
+ * footprint exceeds the whole budget.  *ticket identifies it from then on. */
+int bsw_solve_submit(bsw_server server, const bsw_solve_request* req, uint64_t* ticket);
+/* *state = one of BSW_REQ_*. */
+int bsw_solve_poll(bsw_server server, uint64_t ticket, int* state);
+/* Blocks until the request is done, failed or cancelled, or timeout_s passes. */
+int bsw_solve_wait(bsw_server server, uint64_t ticket, double timeout_s, int* state);
+/* For a finished request: copies the final state to host_W (may be NULL) and
+ * the statistics, releases the ticket and returns the solve's status
+ * (BSW_OK or BSW_W_NOT_CONVERGED).  A failed or cancelled request returns its
+ * error and is released too.  BSW_E_STATE while queued or running. */
+int bsw_solve_fetch(bsw_server server, uint64_t ticket, void* host_W, bsw_solve_stats* stats);
+/* Queued: dropped before admission.  Running: detached at the next step
+ * boundary.  The ticket stays valid until fetched. */
+int bsw_solve_cancel(bsw_server server, uint64_t ticket);
+/* out8 = {queued, resident, device bytes in use, budget, batched time steps
+ * taken, kernel launches, completed requests, peak resident}. */
+int bsw_server_info(bsw_server server, double* out8);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,16 @@ class SolveStats(C.Structure):
                 ("max_mass_drift", C.c_double), ("active_pct", C.c_double), ("t_end", C.c_double),
                 ("seconds", C.c_double), ("operator_applies", C.c_double),
                 ("jacobian_applies", C.c_double), ("jac_apply_seconds", C.c_double),
-                ("jac_apply_launches", C.c_double)]
+                ("jac_apply_launches", C.c_double), ("queue_seconds", C.c_double)]
+
+
+class SolveRequest(C.Structure):
+    _fields_ = [("n_vert", C.c_int64), ("xy", C.POINTER(C.c_double)), ("n_el", C.c_int64),
+                ("el2vert", C.POINTER(C.c_int32)), ("P", C.c_int32), ("precision", C.c_int32),
+                ("params", Params), ("ic", IC), ("W0", C.c_void_p), ("opts", SolveOpts)]
+
+
+BSW_REQ_QUEUED, BSW_REQ_RUNNING, BSW_REQ_DONE, BSW_REQ_FAILED, BSW_REQ_CANCELLED = range(5)
 
 
 # name -> (restype, argtypes); the exported symbols declared in include/bsw.h
@@ -74,6 +83,15 @@ SIGNATURES = {
     "bsw_norm2": (C.c_int, [_VP, _VP, _DP]),
     "bsw_cfl_dt": (C.c_int, [_VP, C.POINTER(Params), _VP, C.c_double, _DP]),
     "bsw_solve": (C.c_int, [_VP, C.POINTER(Params), C.POINTER(SolveOpts), _VP, C.POINTER(SolveStats)]),
+    "bsw_request_footprint": (C.c_int64, [C.POINTER(SolveRequest)]),
+    "bsw_server_create": (C.c_int, [_VP, C.c_size_t, C.c_int, C.POINTER(_VP)]),
+    "bsw_server_destroy": (C.c_int, [_VP]),
+    "bsw_solve_submit": (C.c_int, [_VP, C.POINTER(SolveRequest), C.POINTER(C.c_uint64)]),
+    "bsw_solve_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_int)]),
+    "bsw_solve_wait": (C.c_int, [_VP, C.c_uint64, C.c_double, C.POINTER(C.c_int)]),
+    "bsw_solve_fetch": (C.c_int, [_VP, C.c_uint64, _VP, C.POINTER(SolveStats)]),
+    "bsw_solve_cancel": (C.c_int, [_VP, C.c_uint64]),
+    "bsw_server_info": (C.c_int, [_VP, _DP]),
 }
 
 _lib = None
@@ -299,3 +317,99 @@ class Disc:
         rc = lib().bsw_solve(self.h, C.byref(params), C.byref(opts.c()), _ptr(W), C.byref(st))
         self._ck(rc)
         return {k: getattr(st, k) for k, _ in SolveStats._fields_}
+
+
+class _ReqArrays:
+    """Keeps the host arrays of a request alive until it is submitted."""
+
+    def __init__(self, xy, el2vert, P, precision, params, ic, opts, W0=None):
+        import numpy as np
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64)
+        self.e2v = np.ascontiguousarray(el2vert, dtype=np.int32)
+        self.W0 = None
+        if W0 is not None:
+            self.W0 = np.ascontiguousarray(W0, dtype=np.float64 if precision == BSW_FP64 else np.float32)
+        r = SolveRequest()
+        r.n_vert = self.xy.shape[0]
+        r.xy = self.xy.ctypes.data_as(_DP)
+        r.n_el = self.e2v.shape[0]
+        r.el2vert = self.e2v.ctypes.data_as(C.POINTER(C.c_int32))
+        r.P = int(P)
+        r.precision = int(precision)
+        r.params = params
+        r.ic = make_ic(ic) if ic is not None else IC()
+        r.W0 = C.c_void_p(self.W0.ctypes.data) if self.W0 is not None else None
+        r.opts = opts.c()
+        self.req = r
+
+
+def request_footprint(n_el: int, P: int, precision: int, gmres_m: int = 30) -> int:
+    """Device bytes a served solve of this size occupies while resident."""
+    r = SolveRequest()
+    r.n_el, r.P, r.precision = int(n_el), int(P), int(precision)
+    r.opts.gmres_m = int(gmres_m)
+    return int(lib().bsw_request_footprint(C.byref(r)))
+
+
+class Server:
+    """bsw_server: a worker thread that batches resident solves (continuous
+    batching at time-step granularity) under a device-memory budget."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_slots: int = 64):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx._check(lib().bsw_server_create(ctx.h, int(budget_bytes), int(max_slots), C.byref(h)), ctx.h)
+        self.h = h
+        self._shape = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bsw_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, xy, el2vert, P: int, precision: int, params: Params, ic=None, opts: Options = None,
+               W0=None) -> int:
+        opts = opts or Options()
+        a = _ReqArrays(xy, el2vert, P, precision, params, ic, opts, W0)
+        t = C.c_uint64(0)
+        self.ctx._check(lib().bsw_solve_submit(self.h, C.byref(a.req), C.byref(t)), self.ctx.h)
+        n_p = (P + 1) * (P + 2) // 2
+        self._shape[t.value] = ((7, n_p, a.req.n_el), precision)
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = C.c_int(0)
+        self.ctx._check(lib().bsw_solve_poll(self.h, C.c_uint64(ticket), C.byref(st)), self.ctx.h)
+        return st.value
+
+    def wait(self, ticket: int, timeout: float = 600.0) -> int:
+        st = C.c_int(0)
+        self.ctx._check(lib().bsw_solve_wait(self.h, C.c_uint64(ticket), float(timeout), C.byref(st)),
+                        self.ctx.h)
+        return st.value
+
+    def fetch(self, ticket: int):
+        """(final state as a numpy array [n_f, n_p, n_el], statistics dict)."""
+        import numpy as np
+        shape, prec = self._shape.pop(ticket)
+        W = np.empty(shape, dtype=np.float64 if prec == BSW_FP64 else np.float32)
+        st = SolveStats()
+        rc = lib().bsw_solve_fetch(self.h, C.c_uint64(ticket), C.c_void_p(W.ctypes.data), C.byref(st))
+        self.ctx._check(rc, self.ctx.h)
+        return W, {k: getattr(st, k) for k, _ in SolveStats._fields_}
+
+    def cancel(self, ticket: int):
+        self.ctx._check(lib().bsw_solve_cancel(self.h, C.c_uint64(ticket)), self.ctx.h)
+
+    def info(self) -> dict:
+        out = (C.c_double * 8)()
+        lib().bsw_server_info(self.h, out)
+        keys = ("queued", "resident", "bytes_in_use", "budget", "steps", "launches", "completed", "peak_resident")
+        return dict(zip(keys, [float(v) for v in out]))
+

@@ -244,13 +244,11 @@ __device__ __forceinline__ void lift_face(const Tab<D, P, T>& tb, int fc, int rr
 // ------------------------------------------------------------------ kernels
 // b_old = (1/dt) <phi, U(W_old)> on the 1+D balance rows.
 template <int D, int P, class T>
-__global__ void __launch_bounds__(256) k_step_begin(const T* __restrict__ W, T* __restrict__ bold, MeshView<T> m,
-                                                     DevParams<T> p) {
+__device__ __forceinline__ void step_begin_elem(const T* __restrict__ W, T* __restrict__ bold, const MeshView<T>& m,
+                                                const DevParams<T>& p, int e) {
   using S = Shape<D, P>;
   const Tab<D, P, T>& tb = tab<D, P, T>();
   const int n = m.n_el;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
   T w[S::NF][S::NP];
   load_coeffs<D, P, T>(W, n, e, w);
   T acc[S::NV][S::NP];
@@ -277,6 +275,13 @@ __global__ void __launch_bounds__(256) k_step_begin(const T* __restrict__ W, T* 
   for (int f = 0; f < S::NV; ++f)
 #pragma unroll
     for (int i = 0; i < S::NP; ++i) bold[(size_t)(f * S::NP + i) * n + e] = acc[f][i];
+}
+
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) k_step_begin(const T* __restrict__ W, T* __restrict__ bold, MeshView<T> m,
+                                                     DevParams<T> p) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m.n_el) step_begin_elem<D, P, T>(W, bold, m, p, e);
 }
 
 // Workgroups are dealt round-robin to the chip's 8 XCDs, each with its own L2.
@@ -313,18 +318,17 @@ struct Blk {
 };
 
 // MODE 0: residual (x unused, bold subtracted); MODE 1: Jacobian product
-// along x (bold unused).
+// along x (bold unused).  One tile: elements e0 .. e0+EB-1 of one mesh.
 template <int D, int P, class T, int MODE>
-__global__ void __launch_bounds__(256) k_elem_blocked(const T* __restrict__ W, const T* __restrict__ x,
-                                                       const T* __restrict__ bold, T* __restrict__ out,
-                                                       MeshView<T> m, DevParams<T> p) {
+__device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const T* __restrict__ x,
+                                                  const T* __restrict__ bold, T* __restrict__ out,
+                                                  const MeshView<T>& m, const DevParams<T>& p, int e0) {
   using S = Shape<D, P>;
   using B = Blk<D, P>;
   constexpr bool TAN = MODE == 1;
   const Tab<D, P, T>& tb = tab<D, P, T>();
   const int n = m.n_el;
   const int tid = threadIdx.x;
-  const int e0 = xcd_tile(blockIdx.x, gridDim.x) * B::EB;
   __shared__ T sW[S::BS][B::EB];
   __shared__ T sX[TAN ? S::BS : 1][TAN ? B::EB : 1];
   __shared__ T sV[S::NQ][B::NVF][B::EB];
@@ -462,6 +466,13 @@ __global__ void __launch_bounds__(256) k_elem_blocked(const T* __restrict__ W, c
   }
 }
 
+template <int D, int P, class T, int MODE>
+__global__ void __launch_bounds__(256) k_elem_blocked(const T* __restrict__ W, const T* __restrict__ x,
+                                                       const T* __restrict__ bold, T* __restrict__ out,
+                                                       MeshView<T> m, DevParams<T> p) {
+  elem_blocked_tile<D, P, T, MODE>(W, x, bold, out, m, p, xcd_tile(blockIdx.x, gridDim.x) * Blk<D, P>::EB);
+}
+
 // Tangent of the element residual.  The perturbation is either a full vector
 // x (matrix-free Jacobian product: own and neighbour coefficients) or the
 // unit vector of one own degree of freedom (a column of the diagonal block).
@@ -551,10 +562,9 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
 // element-major and row-major: blocks[(e * BS + row) * BS + col] (coalesced
 // across the columns of a row).
 template <int D, int P, class T>
-__global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, T* __restrict__ blocks, MeshView<T> m,
-                                                      DevParams<T> p) {
+__device__ __forceinline__ void jac_columns_elem(const T* __restrict__ W, T* __restrict__ blocks,
+                                                 const MeshView<T>& m, const DevParams<T>& p, int e) {
   using S = Shape<D, P>;
-  const int e = blockIdx.x;
   const int col = threadIdx.x;
   if (col >= S::BS) return;
   T acc[S::NF][S::NP];
@@ -566,19 +576,24 @@ __global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, T*
     for (int i = 0; i < S::NP; ++i) blk[(f * S::NP + i) * S::BS + col] = acc[f][i];
 }
 
+template <int D, int P, class T>
+__global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, T* __restrict__ blocks, MeshView<T> m,
+                                                      DevParams<T> p) {
+  jac_columns_elem<D, P, T>(W, blocks, m, p, blockIdx.x);
+}
+
 // Inverse of one diagonal block per workgroup (one wavefront): LU with
 // partial pivoting staged in LDS (lanes own rows for the pivot search and the
 // elimination), then lane k solves L U y = P e_k for column k of the inverse.
 // The inverse is written element-fastest, Ainv[(row * BS + col) * n + e], so
 // the preconditioner apply is a coalesced batched mat-vec.
 template <int BS, class T>
-__global__ void __launch_bounds__(64) k_block_inverse(const T* __restrict__ A, T* __restrict__ Ainv, int n) {
+__device__ __forceinline__ void block_inverse_elem(const T* __restrict__ A, T* __restrict__ Ainv, int n, int e) {
   constexpr int LD = BS + 1;
   constexpr int RPL = (BS + 63) / 64;  // rows per lane
   __shared__ T a[BS * LD];
   __shared__ int pr[BS];
   __shared__ int piv_s;
-  const int e = blockIdx.x;
   const int lane = threadIdx.x;
   const T* src = A + (size_t)e * BS * BS;
   for (int idx = lane; idx < BS * BS; idx += 64) a[(idx / BS) * LD + idx % BS] = src[idx];
@@ -654,18 +669,67 @@ __global__ void __launch_bounds__(64) k_block_inverse(const T* __restrict__ A, T
   }
 }
 
+template <int BS, class T>
+__global__ void __launch_bounds__(64) k_block_inverse(const T* __restrict__ A, T* __restrict__ Ainv, int n) {
+  block_inverse_elem<BS, T>(A, Ainv, n, blockIdx.x);
+}
+
 // y = blockdiag(A_e)^{-1} x: one lane per (row, element), element fastest.
 template <int BS, class T>
-__global__ void __launch_bounds__(256) k_block_apply(const T* __restrict__ Ainv, const T* __restrict__ x,
-                                                      T* __restrict__ y, int n) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)BS * n) return;
+__device__ __forceinline__ void block_apply_item(const T* __restrict__ Ainv, const T* __restrict__ x,
+                                                 T* __restrict__ y, int n, int64_t idx) {
   const int row = (int)(idx / n), e = (int)(idx % n);
   const T* arow = Ainv + (size_t)row * BS * n + e;
   T s = T(0);
 #pragma unroll
   for (int j = 0; j < BS; ++j) s += arow[(size_t)j * n] * x[(size_t)j * n + e];
   y[(size_t)row * n + e] = s;
+}
+
+template <int BS, class T>
+__global__ void __launch_bounds__(256) k_block_apply(const T* __restrict__ Ainv, const T* __restrict__ x,
+                                                      T* __restrict__ y, int n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (int64_t)BS * n) block_apply_item<BS, T>(Ainv, x, y, n, idx);
+}
+
+// per-element contributions to the mass, the active (yielded) area, the
+// largest |u| + sqrt(g h) and the smallest depth over the volume points
+template <int D, int P, class T>
+__device__ __forceinline__ void diag_elem(const T* __restrict__ W, const MeshView<T>& m, double g, double thr, int e,
+                                          double (&v)[4]) {
+  using S = Shape<D, P>;
+  const Tab<D, P, T>& tb = tab<D, P, T>();
+  const int n = m.n_el;
+  {
+    T w[S::NF][S::NP];
+    load_coeffs<D, P, T>(W, n, e, w);
+    const double detJ = (double)m.detJ[e];
+#pragma unroll
+    for (int q = 0; q < S::NQ; ++q) {
+      T X[S::NF];
+      interp<D, P, T>(tb.phi[q], w, X);
+      const double wq = (double)tb.qw[q] * detJ;
+      const double h = (double)X[0];
+      v[0] += wq * h;
+      double tr = 0.0, n2 = 0.0, um = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) tr += (double)X[1 + D + a * D + a];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          const double dab = 0.5 * ((double)X[1 + D + b * D + a] + (double)X[1 + D + a * D + b]);
+          n2 += dab * dab;
+        }
+      const double s = sqrt(0.5 * (n2 + tr * tr));
+      if (s - thr >= 0.0) v[1] += wq;
+#pragma unroll
+      for (int b = 0; b < D; ++b) um += (double)X[1 + b] * (double)X[1 + b];
+      v[2] = fmax(v[2], sqrt(um) + sqrt(g * fmax(h, 0.0)));
+      v[3] = fmin(v[3], h);
+    }
+  }
 }
 
 }  // namespace bsw

@@ -322,40 +322,10 @@ __global__ void __launch_bounds__(kRedThreads) k_absmax(const T* __restrict__ x,
 template <int D, int P, class T>
 __global__ void __launch_bounds__(kRedThreads) k_diag(const T* __restrict__ W, MeshView<T> m, double g, double thr,
                                                        double* part) {
-  using S = Shape<D, P>;
-  const Tab<D, P, T>& tb = tab<D, P, T>();
   double v[4] = {0.0, 0.0, 0.0, INFINITY};
   const int ops[4] = {0, 0, 1, 2};
-  const int n = m.n_el;
-  for (int e = blockIdx.x * kRedThreads + threadIdx.x; e < n; e += gridDim.x * kRedThreads) {
-    T w[S::NF][S::NP];
-    load_coeffs<D, P, T>(W, n, e, w);
-    const double detJ = (double)m.detJ[e];
-#pragma unroll
-    for (int q = 0; q < S::NQ; ++q) {
-      T X[S::NF];
-      interp<D, P, T>(tb.phi[q], w, X);
-      const double wq = (double)tb.qw[q] * detJ;
-      const double h = (double)X[0];
-      v[0] += wq * h;
-      double tr = 0.0, n2 = 0.0, um = 0.0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) tr += (double)X[1 + D + a * D + a];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          const double dab = 0.5 * ((double)X[1 + D + b * D + a] + (double)X[1 + D + a * D + b]);
-          n2 += dab * dab;
-        }
-      const double s = sqrt(0.5 * (n2 + tr * tr));
-      if (s - thr >= 0.0) v[1] += wq;
-#pragma unroll
-      for (int b = 0; b < D; ++b) um += (double)X[1 + b] * (double)X[1 + b];
-      v[2] = fmax(v[2], sqrt(um) + sqrt(g * fmax(h, 0.0)));
-      v[3] = fmin(v[3], h);
-    }
-  }
+  for (int e = blockIdx.x * kRedThreads + threadIdx.x; e < m.n_el; e += gridDim.x * kRedThreads)
+    diag_elem<D, P, T>(W, m, g, thr, e, v);
   block_reduce<4>(v, ops, part);
 }
 
@@ -1243,3 +1213,5 @@ extern "C" int bsw_solve(bsw_disc d, const bsw_params* p, const bsw_solve_opts* 
   if (d->precision == BSW_FP64) return solve_impl<double>(d, p, o, (double*)W, st);
   return solve_impl<float>(d, p, o, (float*)W, st);
 }
+
+#include "bsw_batch.hpp"

@@ -31,3 +31,16 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     # the Python binding covers the same names
     assert set(declared_symbols()) == set(bsw.SIGNATURES)
+
+
+def test_request_footprint_is_host_arithmetic():
+    """bsw_request_footprint needs no device: it grows with the mesh and the
+    restart length, and FP32 state takes less than FP64."""
+    from paper_2301_11238_amd import bsw
+    a = bsw.request_footprint(1000, 2, bsw.BSW_FP64)
+    assert a > 1000 * 42 * 8 * 41  # state and 41 work vectors at least
+    assert bsw.request_footprint(2000, 2, bsw.BSW_FP64) > a
+    assert bsw.request_footprint(1000, 2, bsw.BSW_FP32) < a
+    assert bsw.request_footprint(1000, 2, bsw.BSW_FP64, gmres_m=10) < a
+    assert bsw.request_footprint(1000, 3, bsw.BSW_FP64) > a
+    assert bsw.request_footprint(1000, 5, bsw.BSW_FP64) == -1
