@@ -30,7 +30,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
 # scaled by the same counters on a plain copy of known size; None until the
 # counters are taken on the current kernel.
-TRAFFIC_BYTES = {"jacobian_apply": (3916.5 * 2.0 + 2688.0 * 1.0) * 1024}  # counter summary under profiles/
+TRAFFIC_BYTES = {}  # counter summary under profiles/
 
 
 def parse():
@@ -43,6 +43,11 @@ def parse():
     ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
                     help="c2: the 8192-triangle P2 incline (default); c3: the 131072-triangle P3 mesh of the "
                          "circular dam break (kernel timings only)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving comparison (batched FP32 server vs plain FP64 solves)")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-steps", type=int, default=2,
+                    help="time steps per served request (each draw's horizon is cut to this many steps)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solve: a 256 MiB device copy (counter calibration) and 20 launches of each hot "
                          "kernel, for rocprofv3 --pmc passes")
@@ -102,6 +107,101 @@ def cpu_baseline(problem, seconds):
     return dict(value=n_dof * applies / el, unit="DOF-updates/s", cores=threads, kind="oracle",
                 sample=f"{applies} whole-mesh applies (operator + Jacobian, alternating) of the FP64 C oracle "
                        f"on the same 8192-triangle P2 mesh, {el:.1f} s")
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def serving(ctx, n_req, steps, seed=4):
+    """Batched FP32 solve server against plain one-solve-at-a-time FP64 solves
+    on the same request list: draws of the ensemble distribution (circular dam
+    breaks of 500-4000 triangles, P 1-3, random yield stress, viscosity,
+    eps in [1e-5, 1e-2] and regularisation), each cut to `steps` time steps.
+    Throughput: all requests present at t = 0.  Latency: Poisson arrivals at
+    70% of the batched server's measured throughput; the plain method's
+    latencies come from its measured service times in a FIFO queue."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2301_11238_amd import bsw
+    probs = [wl.config4_instance(k, seed, n_range=(500.0, 4000.0)) for k in range(n_req)]
+
+    def opts(p):
+        return bsw.Options(t_end=p.t_end, cfl=p.cfl, max_steps=steps)
+
+    # plain: FP64, one solve at a time (upload, project, solve, copy back)
+    t0 = time.perf_counter()
+    svc, plain_W = [], []
+    for p in probs:
+        a = time.perf_counter()
+        m = bsw.Mesh(ctx, 2, p.xy, p.el2vert)
+        d = bsw.Disc(m, p.P, bsw.BSW_FP64)
+        W = d.project_ic(p.ic)
+        d.solve(bsw.make_params(p.params), opts(p), W)
+        plain_W.append(W.cpu().numpy())
+        svc.append(time.perf_counter() - a)
+        d.close()
+        m.close()
+    T_plain = time.perf_counter() - t0
+
+    def served(prec, arrivals=None):
+        srv = bsw.Server(ctx, 128 << 30, 128)
+        out, lat = [None] * len(probs), []
+        t0 = time.perf_counter()
+        tickets = []
+        for k, p in enumerate(probs):
+            if arrivals is not None:
+                dtw = t0 + arrivals[k] - time.perf_counter()
+                if dtw > 0:
+                    time.sleep(dtw)
+            tickets.append(srv.submit(p.xy, p.el2vert, p.P, prec, bsw.make_params(p.params), ic=p.ic,
+                                      opts=opts(p)))
+        for k, t in enumerate(tickets):
+            srv.wait(t, 3600.0)
+            W, st = srv.fetch(t)
+            out[k] = W
+            lat.append(st["queue_seconds"] + st["seconds"])
+        T = time.perf_counter() - t0
+        info = srv.info()
+        srv.close()
+        return T, out, lat, info
+
+    T32, W32, lat32_closed, info32 = served(bsw.BSW_FP32)
+    T64, W64, _, _ = served(bsw.BSW_FP64)
+    # accuracy of the batched FP32 results against the plain FP64 ones:
+    # relative L2 of the depth and velocity coefficients (fields h, u1, u2)
+    err = 0.0
+    for a, b in zip(W32, plain_W):
+        a = a.astype(np.float64)
+        err = max(err, float(np.linalg.norm(a[:3] - b[:3]) / np.linalg.norm(b[:3])))
+    ident = all(np.array_equal(a, b) for a, b in zip(W64, plain_W))
+    max64 = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(W64, plain_W))
+    # open loop at 70% of the batched throughput
+    rate = 0.7 * n_req / T32
+    rng = np.random.default_rng(5)
+    arr = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    arr -= arr[0]
+    _, _, lat32, _ = served(bsw.BSW_FP32, arrivals=arr)
+    done, lat_plain = 0.0, []
+    for a, s_ in zip(arr, svc):
+        done = max(done, a) + s_
+        lat_plain.append(done - a)
+    return {
+        "requests": n_req, "steps_per_request": steps,
+        "workload": "ensemble draws (circular dam breaks, 500-4000 triangles, P 1-3, eps 1e-5..1e-2, regs 1-3)",
+        "plain_fp64": {"solves_per_s": n_req / T_plain, "seconds": T_plain,
+                       "p50_s": pct(lat_plain, 50), "p99_s": pct(lat_plain, 99)},
+        "batched_fp32": {"solves_per_s": n_req / T32, "seconds": T32, "p50_s": pct(lat32, 50),
+                         "p99_s": pct(lat32, 99), "closed_loop_p50_s": pct(lat32_closed, 50),
+                         "peak_resident": info32["peak_resident"], "launches": info32["launches"],
+                         "rel_l2_vs_plain_fp64": err},
+        "batched_fp64": {"solves_per_s": n_req / T64, "seconds": T64, "max_rel_diff_vs_plain": max64,
+                         "bitwise_equal_to_plain": ident},
+        "open_loop_rate_per_s": rate,
+        "speedup_fp32_batched_vs_plain_fp64": T_plain / T32,
+    }
 
 
 def main():
@@ -176,7 +276,8 @@ def main():
     achieved = k["bytes"] / k["seconds"] / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES.get(dominant),
-            "kernel": "k_elem_blocked<2,2,double,1> (matrix-free Jacobian apply)",
+            "kernel": "k_trace<2,2,double> + k_elem_blocked<2,2,double,1> (matrix-free Jacobian apply: "
+                      "face traces of x, then the element pass)",
             "bytes_per_launch": k["bytes"], "launch_seconds": k["seconds"],
             "launches_timed": st.get("jac_apply_launches", 0)}
     if args.kernels_only:
@@ -210,6 +311,8 @@ def main():
         "kernels": {name: {"ms": 1e3 * v["seconds"], "GB/s": v["bytes"] / v["seconds"] / 1e9}
                     for name, v in kern.items()},
     }
+    if not args.no_serving:
+        out["serving"] = serving(ctx, args.serve_requests, args.serve_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
     print(json.dumps(out))

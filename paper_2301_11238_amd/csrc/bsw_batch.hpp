@@ -66,6 +66,7 @@ int64_t instance_bytes(int64_t n_el, int P, int precision, int M) {
   const int64_t ntile = (len + kVT - 1) / kVT, ntile_e = (n_el + 255) / 256;
   int64_t b = (kBaseSlots + M + 1) * ld * w;
   b += 2 * bs * bs * n_el * w;
+  b += 3 * 7 * 3 * (P + 1) * n_el * w;  // face traces
   b += std::max<int64_t>(66 * ntile, 4 * ntile_e) * 8;
   b += n_el * (3 * 4 + 6 * 8 + 14 * 8 + (precision == BSW_FP32 ? 14 * 4 : 0));
   return b + 4096;
@@ -207,8 +208,22 @@ struct BatchEngine {
     ++launches;
     return dispatch2<T>(P, f);
   }
-  // mode 0: out = R(W; b_old); mode 1: out = J x
+  // face traces of slot sX into trace set `which` (0 linearisation, 1 residual, 2 Jacobian)
+  int trace(const std::vector<int>& L, int sX, int which) {
+    BatchSet S;
+    const int nt = build(S, L, K_E256);
+    if (!nt) return BSW_OK;
+    auto f = [&]<int D, int PP, class TT>() -> int {
+      hipLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sX, which);
+      HIPCHK(c, hipGetLastError());
+      return BSW_OK;
+    };
+    ++launches;
+    return dispatch2<T>(P, f);
+  }
+  // mode 0: out = R(W; b_old); mode 1: out = J x (each after the trace pass of its argument)
   int elem(int mode, const std::vector<int>& L, int sW, int sX, int sOut) {
+    if (int rc = mode == 0 ? trace(L, sW, 1) : trace(L, sX, 2)) return rc;
     BatchSet S;
     const int nt = build(S, L, K_ETILE);
     if (!nt) return BSW_OK;
@@ -226,6 +241,7 @@ struct BatchEngine {
     return dispatch2<T>(P, f);
   }
   int linearize(const std::vector<int>& L) {
+    if (int rc = trace(L, B_W, 0)) return rc;
     BatchSet S;
     const int nt = build(S, L, K_E1);
     if (!nt) return BSW_OK;
@@ -354,6 +370,9 @@ struct BatchEngine {
     d.len = I->len;
     d.blk = (T*)I->disc->blocks;
     d.blk_raw = (T*)I->disc->blocks_raw;
+    d.trL = (T*)I->disc->trL;
+    d.trA = (T*)I->disc->trA;
+    d.trX = (T*)I->disc->trX;
     d.part = I->part;
     d.ntile = I->ntile;
     d.ntile_e = I->ntile_e;

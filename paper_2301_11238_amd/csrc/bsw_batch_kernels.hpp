@@ -53,6 +53,9 @@ struct InstDesc {
   int64_t len;      // n_f N_p n_el
   T* blk;           // block-Jacobi inverses, [row][col][n_el]
   T* blk_raw;       // diagonal blocks, [n_el][row][col]
+  T* trL;           // face traces of the linearisation state
+  T* trA;           // face traces of the last residual argument
+  T* trX;           // face traces of the last Jacobian argument
   double* part;     // reduction partials, [row][tile]
   int ntile;        // vector tiles: ceil(len / kVT)
   int ntile_e;      // element tiles of 256: ceil(n_el / 256)
@@ -90,7 +93,18 @@ __global__ void __launch_bounds__(256) kb_step_begin(const InstDesc<T>* __restri
   if (e < I.m.n_el) step_begin_elem<D, P, T>(bslot(I, sW, 0), bslot(I, sB, 0), I.m, I.p, e);
 }
 
-// MODE 0: R = residual(W; b_old); MODE 1: y = J(W) x
+// face traces of slot sX into trL (which 0), trA (1) or trX (2); 256 elements per tile
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) kb_trace(const InstDesc<T>* __restrict__ ds, BatchSet A, int sX, int which) {
+  const int ai = bset_find(A, blockIdx.x);
+  const InstDesc<T> I = ds[A.inst[ai]];
+  const int e = (blockIdx.x - A.tile0[ai]) * 256 + threadIdx.x;
+  T* tr = which == 0 ? I.trL : (which == 1 ? I.trA : I.trX);
+  if (e < I.m.n_el) trace_elem<D, P, T>(bslot(I, sX, A.jv[ai]), tr, I.m.n_el, e);
+}
+
+// MODE 0: R = residual(W; b_old) with the traces in trA; MODE 1: y = J(W) x
+// with the traces of W in trL and of x in trX
 template <int D, int P, class T, int MODE>
 __global__ void __launch_bounds__(256) kb_elem(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW, int sX,
                                                 int sB, int sOut) {
@@ -100,14 +114,15 @@ __global__ void __launch_bounds__(256) kb_elem(const InstDesc<T>* __restrict__ d
   const int j = A.jv[ai];
   const int e0 = (b - A.tile0[ai]) * Blk<D, P>::EB;
   elem_blocked_tile<D, P, T, MODE>(bslot(I, sW, j), MODE == 1 ? bslot(I, sX, j) : nullptr,
-                                   MODE == 0 ? bslot(I, sB, j) : nullptr, bslot(I, sOut, j), I.m, I.p, e0);
+                                   MODE == 0 ? bslot(I, sB, j) : nullptr, bslot(I, sOut, j),
+                                   MODE == 0 ? I.trA : I.trL, MODE == 1 ? I.trX : nullptr, I.m, I.p, e0);
 }
 
 template <int D, int P, class T>
 __global__ void __launch_bounds__(128) kb_jac_columns(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW) {
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
-  jac_columns_elem<D, P, T>(bslot(I, sW, 0), I.blk_raw, I.m, I.p, blockIdx.x - A.tile0[ai]);
+  jac_columns_elem<D, P, T>(bslot(I, sW, 0), I.trL, I.blk_raw, I.m, I.p, blockIdx.x - A.tile0[ai]);
 }
 
 template <int BS, class T>

@@ -37,17 +37,46 @@ __device__ __forceinline__ void interp(const T (&phi)[Shape<D, P>::NP], const T 
 }
 
 // neighbour trace: coefficients read from global memory, basis of the
-// neighbour's local face g at its point index rr (reversed along the edge)
+// Face traces: the values of every field at every face point of an element,
+// tr[(f * NFP + kp) * n + e] with kp = face * NFQ + point.  One coalesced pass
+// per state; an element then reads its neighbour's side of a shared face
+// point as NF loads instead of interpolating NF x NP neighbour coefficients.
 template <int D, int P, class T>
-__device__ __forceinline__ void interp_global(const Tab<D, P, T>& tb, int g, int rr, const T* __restrict__ A, int n,
-                                              int nb, T (&X)[Shape<D, P>::NF]) {
+__device__ __forceinline__ void trace_elem(const T* __restrict__ X, T* __restrict__ tr, int n, int e) {
+  using S = Shape<D, P>;
+  const Tab<D, P, T>& tb = tab<D, P, T>();
+  constexpr int NFP = S::NFC * S::NFQ;
+#pragma unroll 1
+  for (int f = 0; f < S::NF; ++f) {
+    T c[S::NP];
 #pragma unroll
-  for (int f = 0; f < Shape<D, P>::NF; ++f) {
-    T s = T(0);
+    for (int i = 0; i < S::NP; ++i) c[i] = X[(size_t)(f * S::NP + i) * n + e];
 #pragma unroll
-    for (int i = 0; i < Shape<D, P>::NP; ++i) s += tb.fphi[g][rr][i] * A[(size_t)(f * Shape<D, P>::NP + i) * n + nb];
-    X[f] = s;
+    for (int kp = 0; kp < NFP; ++kp) {
+      T s = T(0);
+#pragma unroll
+      for (int i = 0; i < S::NP; ++i) s += tb.fphi[kp / S::NFQ][kp % S::NFQ][i] * c[i];
+      tr[(size_t)(f * NFP + kp) * n + e] = s;
+    }
   }
+}
+
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) k_trace(const T* __restrict__ X, T* __restrict__ tr, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) trace_elem<D, P, T>(X, tr, n, e);
+}
+
+// the neighbour's values at its local face g, point rr (points run in the
+// opposite direction along a shared edge)
+template <int D, int P, class T>
+__device__ __forceinline__ void load_trace(const T* __restrict__ tr, int n, int nb, int g, int rr,
+                                           T (&X)[Shape<D, P>::NF]) {
+  using S = Shape<D, P>;
+  constexpr int NFP = S::NFC * S::NFQ;
+  const int kp = g * S::NFQ + rr;
+#pragma unroll
+  for (int f = 0; f < S::NF; ++f) X[f] = tr[(size_t)(f * NFP + kp) * n + nb];
 }
 
 template <int D, class T>
@@ -322,6 +351,7 @@ struct Blk {
 template <int D, int P, class T, int MODE>
 __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const T* __restrict__ x,
                                                   const T* __restrict__ bold, T* __restrict__ out,
+                                                  const T* __restrict__ trW, const T* __restrict__ trX,
                                                   const MeshView<T>& m, const DevParams<T>& p, int e0) {
   using S = Shape<D, P>;
   using B = Blk<D, P>;
@@ -413,11 +443,11 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
         if constexpr (TAN) unpack<D, T>(dXm, dsm);
         if (code >= 0) {
           T Xp[S::NF];
-          interp_global<D, P, T>(tb, code & 3, S::NFQ - 1 - rr, W, n, code >> 2, Xp);
+          load_trace<D, P, T>(trW, n, code >> 2, code & 3, S::NFQ - 1 - rr, Xp);
           unpack<D, T>(Xp, sp);
           if constexpr (TAN) {
             T dXp[S::NF];
-            interp_global<D, P, T>(tb, code & 3, S::NFQ - 1 - rr, x, n, code >> 2, dXp);
+            load_trace<D, P, T>(trX, n, code >> 2, code & 3, S::NFQ - 1 - rr, dXp);
             unpack<D, T>(dXp, dsp);
           }
         } else {
@@ -469,15 +499,18 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
 template <int D, int P, class T, int MODE>
 __global__ void __launch_bounds__(256) k_elem_blocked(const T* __restrict__ W, const T* __restrict__ x,
                                                        const T* __restrict__ bold, T* __restrict__ out,
+                                                       const T* __restrict__ trW, const T* __restrict__ trX,
                                                        MeshView<T> m, DevParams<T> p) {
-  elem_blocked_tile<D, P, T, MODE>(W, x, bold, out, m, p, xcd_tile(blockIdx.x, gridDim.x) * Blk<D, P>::EB);
+  elem_blocked_tile<D, P, T, MODE>(W, x, bold, out, trW, trX, m, p,
+                                   xcd_tile(blockIdx.x, gridDim.x) * Blk<D, P>::EB);
 }
 
 // Tangent of the element residual.  The perturbation is either a full vector
 // x (matrix-free Jacobian product: own and neighbour coefficients) or the
 // unit vector of one own degree of freedom (a column of the diagonal block).
 template <int D, int P, class T, bool COLUMN>
-__device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __restrict__ W, const T* __restrict__ x,
+__device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __restrict__ W, const T* __restrict__ trW,
+                                             const T* __restrict__ x, const T* __restrict__ trX,
                                              const MeshView<T>& m, const DevParams<T>& p, int e, int col,
                                              T (&acc)[Shape<D, P>::NF][Shape<D, P>::NP]) {
   using S = Shape<D, P>;
@@ -535,7 +568,7 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
       unpack<D, T>(dXm, dsm);
       if (code >= 0) {
         T Xp[S::NF];
-        interp_global<D, P, T>(tb, code & 3, S::NFQ - 1 - rr, W, n, code >> 2, Xp);
+        load_trace<D, P, T>(trW, n, code >> 2, code & 3, S::NFQ - 1 - rr, Xp);
         unpack<D, T>(Xp, sp);
         if constexpr (COLUMN) {
           T z[S::NF];
@@ -544,7 +577,7 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
           unpack<D, T>(z, dsp);
         } else {
           T dXp[S::NF];
-          interp_global<D, P, T>(tb, code & 3, S::NFQ - 1 - rr, x, n, code >> 2, dXp);
+          load_trace<D, P, T>(trX, n, code >> 2, code & 3, S::NFQ - 1 - rr, dXp);
           unpack<D, T>(dXp, dsp);
         }
       } else {
@@ -562,13 +595,14 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
 // element-major and row-major: blocks[(e * BS + row) * BS + col] (coalesced
 // across the columns of a row).
 template <int D, int P, class T>
-__device__ __forceinline__ void jac_columns_elem(const T* __restrict__ W, T* __restrict__ blocks,
-                                                 const MeshView<T>& m, const DevParams<T>& p, int e) {
+__device__ __forceinline__ void jac_columns_elem(const T* __restrict__ W, const T* __restrict__ trW,
+                                                 T* __restrict__ blocks, const MeshView<T>& m, const DevParams<T>& p,
+                                                 int e) {
   using S = Shape<D, P>;
   const int col = threadIdx.x;
   if (col >= S::BS) return;
   T acc[S::NF][S::NP];
-  elem_tangent<D, P, T, true>(tab<D, P, T>(), W, nullptr, m, p, e, col, acc);
+  elem_tangent<D, P, T, true>(tab<D, P, T>(), W, trW, nullptr, nullptr, m, p, e, col, acc);
   T* blk = blocks + (size_t)e * S::BS * S::BS;
 #pragma unroll
   for (int f = 0; f < S::NF; ++f)
@@ -577,9 +611,9 @@ __device__ __forceinline__ void jac_columns_elem(const T* __restrict__ W, T* __r
 }
 
 template <int D, int P, class T>
-__global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, T* __restrict__ blocks, MeshView<T> m,
-                                                      DevParams<T> p) {
-  jac_columns_elem<D, P, T>(W, blocks, m, p, blockIdx.x);
+__global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, const T* __restrict__ trW,
+                                                      T* __restrict__ blocks, MeshView<T> m, DevParams<T> p) {
+  jac_columns_elem<D, P, T>(W, trW, blocks, m, p, blockIdx.x);
 }
 
 // Inverse of one diagonal block per workgroup (one wavefront): LU with

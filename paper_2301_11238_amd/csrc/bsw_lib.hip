@@ -63,6 +63,11 @@ struct bsw_disc_s {
   double lin_dt = 0.0;
   void* blocks = nullptr;      // block inverses, [row][col][n_el]
   void* blocks_raw = nullptr;  // unfactored blocks, [n_el][row][col]
+  // face traces (field values at every face point): of the linearisation
+  // state, of the last operator argument and of the last Jacobian argument
+  void* trL = nullptr;
+  void* trA = nullptr;
+  void* trX = nullptr;
   // reduction scratch
   double* part = nullptr;
   size_t part_len = 0;
@@ -454,8 +459,10 @@ struct OpLaunch {
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
-    hipLaunchKernelGGL((k_elem_blocked<D, P, T, 0>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0,
-                       d->mesh->ctx->stream, (const T*)W, (const T*)nullptr, (const T*)bold, (T*)R, m,
+    hipStream_t st = d->mesh->ctx->stream;
+    hipLaunchKernelGGL((k_trace<D, P, T>), grid1(m.n_el), dim3(256), 0, st, (const T*)W, (T*)d->trA, m.n_el);
+    hipLaunchKernelGGL((k_elem_blocked<D, P, T, 0>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0, st, (const T*)W,
+                       (const T*)nullptr, (const T*)bold, (T*)R, (const T*)d->trA, (const T*)nullptr, m,
                        devparams<T>(*p, dt));
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
@@ -477,17 +484,25 @@ struct StepBeginLaunch {
 struct JacApplyLaunch {
   bsw_disc d; const void* x; void* y;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional: timestamps of this dispatch
+  // the trace pass and the element pass; with events, ev_start stamps the
+  // start of the first and ev_stop the end of the second
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
-    if (ev_start)
-      hipExtLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0,
-                            d->mesh->ctx->stream, ev_start, ev_stop, 0, (const T*)d->lin_W, (const T*)x,
-                            (const T*)nullptr, (T*)y, m, devparams<T>(d->lin_prm, d->lin_dt));
-    else
-      hipLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0,
-                         d->mesh->ctx->stream, (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, m,
-                         devparams<T>(d->lin_prm, d->lin_dt));
+    hipStream_t st = d->mesh->ctx->stream;
+    const dim3 gt = grid1(m.n_el), ge = grid1(m.n_el, Blk<D, P>::EB);
+    const T* tL = (const T*)d->trL;
+    T* tX = (T*)d->trX;
+    const auto prm = devparams<T>(d->lin_prm, d->lin_dt);
+    if (ev_start) {
+      hipExtLaunchKernelGGL((k_trace<D, P, T>), gt, dim3(256), 0, st, ev_start, nullptr, 0, (const T*)x, tX, m.n_el);
+      hipExtLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), ge, dim3(256), 0, st, nullptr, ev_stop, 0,
+                            (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, tL, (const T*)tX, m, prm);
+    } else {
+      hipLaunchKernelGGL((k_trace<D, P, T>), gt, dim3(256), 0, st, (const T*)x, tX, m.n_el);
+      hipLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), ge, dim3(256), 0, st, (const T*)d->lin_W, (const T*)x,
+                         (const T*)nullptr, (T*)y, tL, (const T*)tX, m, prm);
+    }
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -501,8 +516,10 @@ struct LinearizeLaunch {
     auto m = view<T>(d);
     bsw_ctx c = d->mesh->ctx;
     const int tpb = S::BS <= 64 ? 64 : 128;
+    hipLaunchKernelGGL((k_trace<D, P, T>), grid1(m.n_el), dim3(256), 0, c->stream, (const T*)d->lin_W, (T*)d->trL,
+                       m.n_el);
     hipLaunchKernelGGL((k_jac_columns<D, P, T>), dim3(m.n_el), dim3(tpb), 0, c->stream, (const T*)d->lin_W,
-                       (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt));
+                       (const T*)d->trL, (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt));
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL((k_block_inverse<S::BS, T>), dim3(m.n_el), dim3(64), 0, c->stream,
                        (const T*)d->blocks_raw, (T*)d->blocks, m.n_el);
@@ -899,7 +916,11 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
     if (int rc = dispatch(d, st)) { delete d; return rc; }
     c->tables_staged[precision][ci] = true;
   }
-  int rc = dev_alloc(c, &d->red_out, 64);
+  const size_t ntr = (size_t)d->ref.nf * d->ref.nfc * d->ref.nfq * M->n_el * d->wsize;
+  int rc = BSW_OK;
+  for (void** t : {&d->trL, &d->trA, &d->trX})
+    if (!rc && hipMalloc(t, ntr) != hipSuccess) rc = fail(c, BSW_E_OOM, "face-trace storage");
+  if (!rc) rc = dev_alloc(c, &d->red_out, 64);
   if (!rc) rc = dev_alloc(c, &d->hcoef, 80);
   if (!rc && hipHostMalloc((void**)&d->red_host, 80 * sizeof(double), hipHostMallocMapped) != hipSuccess)
     rc = fail(c, BSW_E_OOM, "hipHostMalloc");
@@ -913,6 +934,7 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
 int bsw_disc_destroy(bsw_disc d) {
   if (!d) return BSW_OK;
   hfree(d->blocks); hfree(d->blocks_raw); hfree(d->part); hfree(d->red_out);
+  hfree(d->trL); hfree(d->trA); hfree(d->trX);
   hfree(d->gm); hfree(d->hcoef);
   if (d->red_host) (void)hipHostFree(d->red_host);
   delete d;
