@@ -35,40 +35,25 @@ namespace {
 enum BSlot { B_W = 0, B_BOLD, B_R, B_RT, B_RHS, B_DW, B_WT, B_WK, B_Z, B_U, B_V0 };
 constexpr int kBaseSlots = B_V0;
 
-template <class T, class F>
-int dispatch2(int P, F& f) {
-  switch (P) {
-    case 1: return f.template operator()<2, 1, T>();
-    case 2: return f.template operator()<2, 2, T>();
-    case 3: return f.template operator()<2, 3, T>();
-  }
-  return BSW_E_ARG;
-}
-
-int tri_np(int P) { return (P + 1) * (P + 2) / 2; }
-int tri_eb(int P) {  // elements per workgroup of the blocked element kernels
-  switch (P) {
-    case 1: return Blk<2, 1>::EB;
-    case 2: return Blk<2, 2>::EB;
-    case 3: return Blk<2, 3>::EB;
-  }
-  return 1;
-}
+int n_modes(int dim, int P) { return dim == 1 ? P + 1 : (P + 1) * (P + 2) / 2; }
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Device bytes one resident 2-D instance takes: state and Krylov vectors,
-// diagonal blocks and their inverses, reduction partials, mesh arrays.
-int64_t instance_bytes(int64_t n_el, int P, int precision, int M) {
+// Device bytes one resident instance takes: state and Krylov vectors,
+// diagonal blocks and their inverses, face traces, reduction partials, mesh.
+int64_t instance_bytes(int64_t n_el, int dim, int P, int precision, int M) {
   const int64_t w = precision == BSW_FP64 ? 8 : 4;
-  const int64_t bs = 7 * tri_np(P);
+  const int64_t nf = 1 + dim + dim * dim;
+  const int64_t bs = nf * n_modes(dim, P);
+  const int64_t nfp = (dim + 1) * (dim == 1 ? 1 : P + 1);
   const int64_t len = bs * n_el;
   const int64_t ld = round_up(len, 64);
   const int64_t ntile = (len + kVT - 1) / kVT, ntile_e = (n_el + 255) / 256;
   int64_t b = (kBaseSlots + M + 1) * ld * w;
-  b += 2 * bs * bs * n_el * w;
-  b += 3 * 7 * 3 * (P + 1) * n_el * w;  // face traces
-  b += std::max<int64_t>(66 * ntile, 4 * ntile_e) * 8;
-  b += n_el * (3 * 4 + 6 * 8 + 14 * 8 + (precision == BSW_FP32 ? 14 * 4 : 0));
+  b += bs * bs * n_el * (w + 4);  // diagonal blocks and their FP32 inverses
+  b += 3 * nf * nfp * n_el * w;  // face traces
+  b += std::max<int64_t>(std::max<int64_t>(66 * ntile, 4 * ntile_e), 4096) * 8;
+  const int64_t geo = dim * dim + 1 + (dim + 1) * (dim + 1);
+  b += n_el * ((dim + 1) * 4 + (dim + 1) * dim * 8 + geo * 8 + (precision == BSW_FP32 ? geo * 4 : 0));
   return b + 4096;
 }
 
@@ -98,24 +83,27 @@ struct BInst {
   std::vector<double> H, cs, sn, g, y;
   int j = 0, iters = 0, cycles = 0;
   double bn = 0, beta = 0, relres = 0, rtol = 0, hn = 0;
-  bool fold = true, cyc_conv = false;
+  bool cyc_conv = false;
+  bool own = true;  // mesh, discretisation and workspace belong to the instance
   bool finished() const { return failed || cancelled || step >= nsteps; }
 };
 
 template <class T>
 void free_instance(BInst<T>* I) {
   if (!I) return;
-  hfree(I->ws);
-  hfree(I->part);
-  if (I->disc) bsw_disc_destroy(I->disc);
-  if (I->mesh) bsw_mesh_destroy(I->mesh);
+  if (I->own) {
+    hfree(I->ws);
+    hfree(I->part);
+    if (I->disc) bsw_disc_destroy(I->disc);
+    if (I->mesh) bsw_mesh_destroy(I->mesh);
+  }
   delete I;
 }
 
 template <class T>
 struct BatchEngine {
   bsw_ctx c = nullptr;
-  int P = 0, M = 30, EB = 1, BS = 1;
+  int dim = 2, P = 0, M = 30, EB = 1, BS = 1, NFNFC = 1;
   BInst<T>* slots[kMaxBatch] = {};
   InstDesc<T>* d_desc = nullptr;  // device
   InstDesc<T>* h_desc = nullptr;  // pinned staging of the descriptors
@@ -126,6 +114,7 @@ struct BatchEngine {
   int64_t ticks = 0, launches = 0;
 
   ~BatchEngine() {
+    destroy_events();
     for (auto& s : slots) { free_instance(s); s = nullptr; }
     hfree(d_desc);
     hfree(sc);
@@ -134,10 +123,15 @@ struct BatchEngine {
     if (ystage) (void)hipHostFree(ystage);
   }
 
-  int init(bsw_ctx ctx, int P_, int M_) {
-    c = ctx; P = P_; M = M_;
-    EB = tri_eb(P);
-    BS = 7 * tri_np(P);
+  int init(bsw_ctx ctx, int dim_, int P_, int M_) {
+    c = ctx; dim = dim_; P = P_; M = M_;
+    auto fs = [&]<int D, int PP, class TT>() -> int {
+      EB = Blk<D, PP>::EB;
+      BS = Shape<D, PP>::BS;
+      NFNFC = Shape<D, PP>::NF * Shape<D, PP>::NFC;
+      return BSW_OK;
+    };
+    if (dispatchT<T>(dim, P, fs)) return fail(c, BSW_E_ARG, "unsupported order for this dimension");
     if (int rc = dev_alloc(c, &d_desc, kMaxBatch)) return rc;
     if (int rc = dev_alloc(c, &sc, (size_t)kMaxBatch * kScStride)) return rc;
     HIPCHK(c, hipHostMalloc((void**)&h_desc, sizeof(InstDesc<T>) * kMaxBatch, hipHostMallocDefault));
@@ -160,7 +154,7 @@ struct BatchEngine {
   }
 
   // ------------------------------------------------------------ launch sets
-  enum Kind { K_ETILE, K_E256, K_E1, K_ITEM, K_VEC, K_ONE };
+  enum Kind { K_ETILE, K_E256, K_E1, K_ITEM, K_VEC, K_ONE, K_TRACE };
   int tiles_of(const BInst<T>* I, int kind) const {
     switch (kind) {
       case K_ETILE: return (int)((I->n_el + EB - 1) / EB);
@@ -168,18 +162,20 @@ struct BatchEngine {
       case K_E1: return (int)I->n_el;
       case K_ITEM: return (int)((BS * I->n_el + 255) / 256);
       case K_VEC: return I->ntile;
+      case K_TRACE: return (int)((NFNFC * I->n_el + 255) / 256);
     }
     return 1;
   }
-  // fills inst, tile0 and jv (the Krylov index); rows and s are zeroed
-  int build(BatchSet& S, const std::vector<int>& L, int kind) const {
+  // fills inst, tile0 and jv (the Krylov index: jv[a] if given, else the
+  // instance's current one); rows and s are zeroed
+  int build(BatchSet& S, const std::vector<int>& L, int kind, const std::vector<int>* jv = nullptr) const {
     S.n = (int)L.size();
     int tot = 0;
     for (size_t a = 0; a < L.size(); ++a) {
       const BInst<T>* I = slots[L[a]];
       S.inst[a] = (uint16_t)L[a];
       S.tile0[a] = tot;
-      S.jv[a] = (uint8_t)I->j;
+      S.jv[a] = (uint8_t)(jv ? (*jv)[a] : I->j);
       S.rows[a] = 0;
       S.s[a] = 0.0;
       tot += tiles_of(I, kind);
@@ -206,12 +202,12 @@ struct BatchEngine {
       return BSW_OK;
     };
     ++launches;
-    return dispatch2<T>(P, f);
+    return dispatchT<T>(dim, P, f);
   }
   // face traces of slot sX into trace set `which` (0 linearisation, 1 residual, 2 Jacobian)
   int trace(const std::vector<int>& L, int sX, int which) {
     BatchSet S;
-    const int nt = build(S, L, K_E256);
+    const int nt = build(S, L, K_TRACE);
     if (!nt) return BSW_OK;
     auto f = [&]<int D, int PP, class TT>() -> int {
       hipLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sX, which);
@@ -219,7 +215,7 @@ struct BatchEngine {
       return BSW_OK;
     };
     ++launches;
-    return dispatch2<T>(P, f);
+    return dispatchT<T>(dim, P, f);
   }
   // mode 0: out = R(W; b_old); mode 1: out = J x (each after the trace pass of its argument)
   int elem(int mode, const std::vector<int>& L, int sW, int sX, int sOut) {
@@ -238,7 +234,7 @@ struct BatchEngine {
       return BSW_OK;
     };
     ++launches;
-    return dispatch2<T>(P, f);
+    return dispatchT<T>(dim, P, f);
   }
   int linearize(const std::vector<int>& L) {
     if (int rc = trace(L, B_W, 0)) return rc;
@@ -250,12 +246,13 @@ struct BatchEngine {
       hipLaunchKernelGGL((kb_jac_columns<D, PP, TT>), dim3(nt), dim3(Sh::BS <= 64 ? 64 : 128), 0, c->stream,
                          d_desc, S, (int)B_W);
       HIPCHK(c, hipGetLastError());
-      hipLaunchKernelGGL((kb_block_inverse<Sh::BS, TT>), dim3(nt), dim3(64), 0, c->stream, d_desc, S);
+      hipLaunchKernelGGL((kb_block_inverse<Sh::BS, TT>), dim3(nt), dim3(inv_threads<Sh::BS>()), 0, c->stream, d_desc,
+                         S);
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
     launches += 2;
-    return dispatch2<T>(P, f);
+    return dispatchT<T>(dim, P, f);
   }
   int prec(const std::vector<int>& L, int sX, int sY) {
     BatchSet S;
@@ -268,7 +265,7 @@ struct BatchEngine {
       return BSW_OK;
     };
     ++launches;
-    return dispatch2<T>(P, f);
+    return dispatchT<T>(dim, P, f);
   }
 
   // ------------------------------------------------------------ vector stages
@@ -301,9 +298,11 @@ struct BatchEngine {
     return BSW_OK;
   }
   // fold the partials of rows[] rows per instance into sc / sch at offset off
-  int final_rows(const std::vector<int>& L, const std::vector<int>& rows, int etile, unsigned ops, int off) {
+  // (scl, sig: as kb_rows_final; jv: per-instance Krylov index)
+  int final_rows(const std::vector<int>& L, const std::vector<int>& rows, int etile, unsigned ops, int off,
+                 int scl = 0, int sig = -1, const std::vector<int>* jv = nullptr) {
     BatchSet S;
-    build(S, L, K_ONE);
+    build(S, L, K_ONE, jv);
     int mr = 0;
     for (size_t k = 0; k < L.size(); ++k) {
       S.rows[k] = (uint8_t)rows[k];
@@ -311,28 +310,14 @@ struct BatchEngine {
     }
     if (!mr) return BSW_OK;
     hipLaunchKernelGGL((kb_rows_final<T>), dim3((unsigned)L.size(), mr), dim3(256), 0, c->stream, d_desc, S, etile,
-                       ops, sc, sch_dev, off);
+                       ops, sc, sch_dev, off, scl, sig);
     HIPCHK(c, hipGetLastError());
     ++launches;
     return BSW_OK;
   }
-  // V_r . w for r < rows[k] - self, plus w . w as the last row when self
-  int multidot(const std::vector<int>& L, const std::vector<int>& rows, int sw, int self, int off) {
-    BatchSet S;
-    const int nt = build(S, L, K_VEC);
-    if (!nt) return BSW_OK;
-    int mr = 0;
-    for (size_t k = 0; k < L.size(); ++k) {
-      S.rows[k] = (uint8_t)rows[k];
-      mr = std::max(mr, rows[k]);
-    }
-    hipLaunchKernelGGL((kb_multidot<T>), dim3(nt, mr), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, sw, self);
-    HIPCHK(c, hipGetLastError());
-    ++launches;
-    return final_rows(L, rows, 0, 0u, off);
-  }
-  // op 0: sum of squares, 1: max |x|, of slot s0 (and s1 >= 0) -> rows 0 (1) at off
-  int vred(const std::vector<int>& L, int s0, int s1, int op, int off) {
+  // op 0: sum of squares, 1: max |x|, of slot s0 (and s1 >= 0) -> rows 0 (1)
+  // at off; sig >= 0 (op 0): the norm is written and sigma_{jv + sig} = 1 / norm
+  int vred(const std::vector<int>& L, int s0, int s1, int op, int off, int sig = -1) {
     BatchSet S;
     const int nt = build(S, L, K_VEC);
     if (!nt) return BSW_OK;
@@ -342,7 +327,7 @@ struct BatchEngine {
     ++launches;
     std::vector<int> rows(L.size(), nr);
     const unsigned ops = op == 0 ? 0u : (1u | (1u << 2));
-    return final_rows(L, rows, 0, ops, off);
+    return final_rows(L, rows, 0, ops, off, 0, sig);
   }
   int diag(const std::vector<int>& L) {
     BatchSet S;
@@ -354,7 +339,7 @@ struct BatchEngine {
       return BSW_OK;
     };
     ++launches;
-    if (int rc = dispatch2<T>(P, f)) return rc;
+    if (int rc = dispatchT<T>(dim, P, f)) return rc;
     std::vector<int> rows(L.size(), 4);
     return final_rows(L, rows, 1, 0u | (0u << 2) | (1u << 4) | (2u << 6), kScB);
   }
@@ -368,7 +353,7 @@ struct BatchEngine {
     d.ws = I->ws;
     d.ld = I->ld;
     d.len = I->len;
-    d.blk = (T*)I->disc->blocks;
+    d.blk = (float*)I->disc->blocks;
     d.blk_raw = (T*)I->disc->blocks_raw;
     d.trL = (T*)I->disc->trL;
     d.trA = (T*)I->disc->trA;
@@ -384,8 +369,15 @@ struct BatchEngine {
   }
 
   // ------------------------------------------------------------ admission
-  // takes ownership of I; its device arrays are allocated here
-  int add(BInst<T>* I, const void* W0_host, const bsw_ic* ic) {
+  static int64_t part_len(int64_t len, int64_t n_el) {
+    return std::max<int64_t>(std::max<int64_t>(66 * ((len + kVT - 1) / kVT), 4 * ((n_el + 255) / 256)), 4096);
+  }
+  static int64_t ws_len(int64_t len, int M) { return (int64_t)(kBaseSlots + M + 1) * round_up(len, 64); }
+
+  // Puts I in a free slot.  Its workspace and partials are allocated here
+  // unless the caller provided them; the initial state comes from W0 (host
+  // when w0_dev == 0, device otherwise) or the projection of ic.
+  int add(BInst<T>* I, const void* W0, int w0_dev, const bsw_ic* ic) {
     const int k = free_slot();
     if (k < 0) return fail(c, BSW_E_STATE, "batch is full");
     bsw_disc d = I->disc;
@@ -395,13 +387,17 @@ struct BatchEngine {
     I->ntile = (int)((I->len + kVT - 1) / kVT);
     I->ntile_e = (int)((I->n_el + 255) / 256);
     const size_t nb = (size_t)BS * BS * I->n_el;
-    if (hipMalloc((void**)&I->ws, sizeof(T) * (size_t)(kBaseSlots + M + 1) * I->ld) != hipSuccess ||
-        hipMalloc(&d->blocks, nb * sizeof(T)) != hipSuccess || hipMalloc(&d->blocks_raw, nb * sizeof(T)) != hipSuccess)
-      return fail(c, BSW_E_OOM, "instance storage");
-    if (int rc = dev_alloc(c, &I->part, (size_t)std::max<int64_t>(66 * I->ntile, 4 * I->ntile_e))) return rc;
+    if (!I->ws && hipMalloc((void**)&I->ws, sizeof(T) * (size_t)ws_len(I->len, M)) != hipSuccess)
+      return fail(c, BSW_E_OOM, "instance workspace");
+    if ((!d->blocks && hipMalloc(&d->blocks, nb * sizeof(float)) != hipSuccess) ||
+        (!d->blocks_raw && hipMalloc(&d->blocks_raw, nb * sizeof(T)) != hipSuccess))
+      return fail(c, BSW_E_OOM, "block-Jacobi storage");
+    if (!I->part)
+      if (int rc = dev_alloc(c, &I->part, (size_t)part_len(I->len, I->n_el))) return rc;
     T* W = I->ws + (size_t)B_W * I->ld;
-    if (W0_host) {
-      HIPCHK(c, hipMemcpyAsync(W, W0_host, sizeof(T) * I->len, hipMemcpyHostToDevice, c->stream));
+    if (W0) {
+      HIPCHK(c, hipMemcpyAsync(W, W0, sizeof(T) * I->len, w0_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                               c->stream));
     } else {
       if (int rc = bsw_project_ic(d, ic, W)) return rc;
     }
@@ -441,152 +437,260 @@ struct BatchEngine {
     return I;
   }
 
-  // ------------------------------------------------------------ GMRES (lockstep)
+  // ------------------------------------------------------------ GMRES (lockstep, pipelined)
   // Right-preconditioned restarted GMRES(M) with classical Gram-Schmidt done
-  // twice, per instance: J x = rhs to ||rhs - J x|| <= rtol ||rhs||, x = B_DW
-  // starting at 0.  The folded norm ||w - V h2||^2 = w.w - |h2|^2 is used
-  // unless it cancels, then the norm is taken explicitly.
+  // twice, per instance: J x = rhs to ||rhs - J x|| <= rtol ||rhs|| with
+  // x = B_DW starting at 0.  One Arnoldi step of every participating instance
+  // is nine launches (preconditioner, traces, Jacobian, dots, fused
+  // subtraction and dots, new vector and its norm, three folds); the
+  // Hessenberg column, Givens rotations and the cycle test run on the host
+  // from the mapped scalars.  The host issues step t+1 before it reads step
+  // t (Krylov index and iteration cap known in advance), so the device never
+  // waits on the host; a step issued for an instance whose cycle turned out
+  // to end at t is discarded (it only wrote scratch vectors and V_{j+2}).
+  struct Tick {
+    std::vector<int> mem, jv;
+    int parity = 0;
+  };
+  hipEvent_t tick_ev[2] = {nullptr, nullptr};
+  hipEvent_t jt0[2] = {nullptr, nullptr}, jt1[2] = {nullptr, nullptr};
+  bool timing = false;
+  double jac_seconds = 0.0, jac_launches = 0.0;
+
+  int ensure_events() {
+    if (tick_ev[0]) return BSW_OK;
+    for (int p = 0; p < 2; ++p) {
+      HIPCHK(c, hipEventCreateWithFlags(&tick_ev[p], hipEventDisableTiming));
+      HIPCHK(c, hipEventCreate(&jt0[p]));
+      HIPCHK(c, hipEventCreate(&jt1[p]));
+    }
+    return BSW_OK;
+  }
+  void destroy_events() {
+    for (int p = 0; p < 2; ++p) {
+      if (tick_ev[p]) (void)hipEventDestroy(tick_ev[p]);
+      if (jt0[p]) (void)hipEventDestroy(jt0[p]);
+      if (jt1[p]) (void)hipEventDestroy(jt1[p]);
+      tick_ev[p] = jt0[p] = jt1[p] = nullptr;
+    }
+  }
+
+  int launch_tick(const Tick& tk) {
+    const std::vector<int>& L = tk.mem;
+    const std::vector<int>* jv = &tk.jv;
+    const int pa = tk.parity;
+    const int offA = pa ? kScA1 : kScA, offB = pa ? kScB1 : kScB;
+    BatchSet S;
+    // z = sigma_j M^{-1} V_j
+    int nt = build(S, L, K_ITEM, jv);
+    auto fp = [&]<int D, int PP, class TT>() -> int {
+      using Sh = Shape<D, PP>;
+      hipLaunchKernelGGL((kb_prec_krylov<Sh::BS, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S,
+                         (const double*)sc, (int)B_V0, (int)B_Z);
+      HIPCHK(c, hipGetLastError());
+      return BSW_OK;
+    };
+    if (int rc = dispatchT<T>(dim, P, fp)) return rc;
+    // w = J z (face traces of z, then the element pass)
+    nt = build(S, L, K_TRACE, jv);
+    BatchSet S2;
+    const int nt2 = build(S2, L, K_ETILE, jv);
+    auto fj = [&]<int D, int PP, class TT>() -> int {
+      if (timing) {
+        hipExtLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, jt0[pa], nullptr, 0, d_desc,
+                              S, (int)B_Z, 2);
+        hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 1>), dim3(nt2), dim3(256), 0, c->stream, nullptr, jt1[pa], 0,
+                              d_desc, S2, (int)B_W, (int)B_Z, (int)B_BOLD, (int)B_WK);
+      } else {
+        hipLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_Z, 2);
+        hipLaunchKernelGGL((kb_elem<D, PP, TT, 1>), dim3(nt2), dim3(256), 0, c->stream, d_desc, S2, (int)B_W,
+                           (int)B_Z, (int)B_BOLD, (int)B_WK);
+      }
+      HIPCHK(c, hipGetLastError());
+      return BSW_OK;
+    };
+    if (int rc = dispatchT<T>(dim, P, fj)) return rc;
+    // pass 1: h1 = V^T w
+    nt = build(S, L, K_VEC, jv);
+    hipLaunchKernelGGL((kb_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
+    HIPCHK(c, hipGetLastError());
+    std::vector<int> rows(L.size());
+    for (size_t a = 0; a < L.size(); ++a) rows[a] = tk.jv[a] + 1;
+    if (int rc = final_rows(L, rows, 0, 0u, offA, 1, -1, jv)) return rc;
+    // pass 2: w -= V h1; h2 = V^T w, w . w
+    hipLaunchKernelGGL((kb_axpy_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
+                       (int)B_V0, (int)B_WK);
+    HIPCHK(c, hipGetLastError());
+    for (auto& r : rows) r += 1;
+    if (int rc = final_rows(L, rows, 0, 0u, offB, 1, -1, jv)) return rc;
+    // V_{j+1} = w - V h2 and its norm (sigma_{j+1} = 1 / norm)
+    hipLaunchKernelGGL((kb_normalize<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offB,
+                       (int)B_V0, (int)B_WK);
+    HIPCHK(c, hipGetLastError());
+    std::fill(rows.begin(), rows.end(), 1);
+    if (int rc = final_rows(L, rows, 0, 0u, kScN + pa, 0, 1, jv)) return rc;
+    launches += 9;
+    HIPCHK(c, hipEventRecord(tick_ev[pa], c->stream));
+    return BSW_OK;
+  }
+
+  // Hessenberg column j = jv of one processed step, Givens rotations, cycle test
+  void arnoldi_update(BInst<T>* I, int k, int j, int pa) {
+    const int offA = pa ? kScA1 : kScA, offB = pa ? kScB1 : kScB;
+    double* H = I->H.data();
+    for (int i = 0; i <= j; ++i) H[(size_t)i * M + j] = rd(k, offA + i) + rd(k, offB + i);
+    I->hn = rd(k, kScN + pa);
+    H[(size_t)(j + 1) * M + j] = I->hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = I->cs[i] * H[(size_t)i * M + j] + I->sn[i] * H[(size_t)(i + 1) * M + j];
+      H[(size_t)(i + 1) * M + j] = -I->sn[i] * H[(size_t)i * M + j] + I->cs[i] * H[(size_t)(i + 1) * M + j];
+      H[(size_t)i * M + j] = t;
+    }
+    const double den = std::hypot(H[(size_t)j * M + j], H[(size_t)(j + 1) * M + j]);
+    I->cs[j] = H[(size_t)j * M + j] / den;
+    I->sn[j] = H[(size_t)(j + 1) * M + j] / den;
+    H[(size_t)j * M + j] = den;
+    H[(size_t)(j + 1) * M + j] = 0.0;
+    I->g[j + 1] = -I->sn[j] * I->g[j];
+    I->g[j] = I->cs[j] * I->g[j];
+    I->cyc_conv = std::fabs(I->g[j + 1]) <= I->rtol * I->bn || I->hn == 0.0;
+    I->iters += 1;
+    I->j = j + 1;
+  }
+
+  // cycle end of the instances in E: x += M^{-1} V y, true residual
+  // rhs - J x -> V_0 (sigma_0 = 1 / its norm); returns after the norms are read
+  int cycle_end(const std::vector<int>& E) {
+    std::vector<int> rows;
+    for (int k : E) {
+      BInst<T>* I = slots[k];
+      const int jj = I->j;
+      const double* H = I->H.data();
+      for (int i = jj - 1; i >= 0; --i) {
+        double t = I->g[i];
+        for (int q = i + 1; q < jj; ++q) t -= H[(size_t)i * M + q] * I->y[q];
+        I->y[i] = t / H[(size_t)i * M + i];
+      }
+      double* st = ystage + (size_t)k * 72;
+      for (int i = 0; i < jj; ++i) st[i] = I->y[i];
+      HIPCHK(c, hipMemcpyAsync(sc + (size_t)k * kScStride + kScY, st, sizeof(double) * jj, hipMemcpyHostToDevice,
+                               c->stream));
+      rows.push_back(jj);
+      I->cycles += 1;
+    }
+    if (int rc = combine(E, rows, kScY, B_WK, B_Z, 1.0, 2 | 8)) return rc;
+    if (int rc = prec(E, B_Z, B_U)) return rc;
+    if (int rc = lin(E, B_DW, B_DW, B_U, 1.0, 1.0, 0)) return rc;
+    if (int rc = elem(1, E, B_W, B_DW, B_WK)) return rc;
+    if (int rc = lin(E, B_V0, B_RHS, B_WK, 1.0, -1.0, 0)) return rc;
+    std::vector<int> zero(E.size(), 0);
+    for (int k : E) slots[k]->j = 0;  // sigma_0 is written at jv + 0
+    if (int rc = vred(E, B_V0, -1, 0, kScN + 3, 0)) return rc;
+    return sync();
+  }
+
   int gmres(const std::vector<int>& N) {
+    if (int rc = ensure_events()) return rc;
     if (int rc = lin(N, B_DW, B_DW, B_DW, 0.0, 0.0, 4)) return rc;
-    if (int rc = vred(N, B_RHS, -1, 0, kScB)) return rc;
+    if (int rc = lin(N, B_V0, B_RHS, B_RHS, 1.0, 0.0, 8)) return rc;
+    for (int k : N) slots[k]->j = 0;
+    if (int rc = vred(N, B_V0, -1, 0, kScN + 2, 0)) return rc;
     if (int rc = sync()) return rc;
-    std::vector<int> G;
-    std::vector<double> s;
+    Tick cur, nxt;
+    int parity = 0;
     for (int k : N) {
       BInst<T>* I = slots[k];
       I->iters = 0;
       I->cycles = 0;
       I->relres = 0.0;
-      I->bn = std::sqrt(rd(k, kScB));
+      I->bn = rd(k, kScN + 2);
       I->beta = I->bn;
-      if (I->bn > 0.0) {
-        G.push_back(k);
-        s.push_back(1.0 / I->bn);
-      }
-    }
-    if (int rc = lin(G, B_V0, B_RHS, B_RHS, 0.0, 0.0, 1 | 8, &s)) return rc;
-    for (int k : G) {
-      BInst<T>* I = slots[k];
       I->j = 0;
-      std::fill(I->g.begin(), I->g.end(), 0.0);
-      I->g[0] = I->beta;
-    }
-    std::vector<int> rows, F, E, Rs, keep;
-    while (!G.empty()) {
-      ++ticks;
-      // Arnoldi step of every instance at its own index j
-      if (int rc = prec(G, B_V0 | kSlotJ, B_Z)) return rc;
-      if (int rc = elem(1, G, B_W, B_Z, B_WK)) return rc;
-      rows.clear();
-      for (int k : G) {
-        slots[k]->iters += 1;
-        rows.push_back(slots[k]->j + 1);
-      }
-      if (int rc = multidot(G, rows, B_WK, 0, kScA)) return rc;
-      if (int rc = combine(G, rows, kScA, B_WK, B_WK, -1.0, 4)) return rc;
-      for (auto& r : rows) r += 1;
-      if (int rc = multidot(G, rows, B_WK, 1, kScB)) return rc;
-      if (int rc = sync()) return rc;
-      F.clear();
-      for (int k : G) {
-        BInst<T>* I = slots[k];
-        const int j = I->j;
-        double hh = 0.0;
-        for (int i = 0; i <= j; ++i) {
-          const double h2 = rd(k, kScB + i);
-          I->H[(size_t)i * M + j] = rd(k, kScA + i) + h2;
-          hh += h2 * h2;
-        }
-        const double ww = rd(k, kScB + j + 1);
-        I->fold = hh <= 1e-4 * ww;
-        if (I->fold) I->hn = std::sqrt(std::max(ww - hh, 0.0));
-        else F.push_back(k);
-      }
-      if (!F.empty()) {
-        std::vector<int> fr;
-        for (int k : F) fr.push_back(slots[k]->j + 1);
-        if (int rc = combine(F, fr, kScB, B_WK, B_WK, -1.0, 4)) return rc;
-        if (int rc = vred(F, B_WK, -1, 0, kScA)) return rc;
-        if (int rc = sync()) return rc;
-        for (int k : F) slots[k]->hn = std::sqrt(rd(k, kScA));
-      }
-      // V_{j+1} = (w - V h2) / hn  (the subtraction already done where not folded)
-      rows.clear();
-      s.clear();
-      for (int k : G) {
-        BInst<T>* I = slots[k];
-        rows.push_back(I->fold ? I->j + 1 : 0);
-        s.push_back(I->hn > 0.0 ? 1.0 / I->hn : 0.0);
-      }
-      if (int rc = combine(G, rows, kScB, B_WK, (B_V0 + 1) | kSlotJ, 1.0, 1, &s)) return rc;
-      // Givens rotations and the cycle test, per instance
-      E.clear();
-      keep.clear();
-      for (int k : G) {
-        BInst<T>* I = slots[k];
-        const int j = I->j;
-        double* H = I->H.data();
-        H[(size_t)(j + 1) * M + j] = I->hn;
-        for (int i = 0; i < j; ++i) {
-          const double t = I->cs[i] * H[(size_t)i * M + j] + I->sn[i] * H[(size_t)(i + 1) * M + j];
-          H[(size_t)(i + 1) * M + j] = -I->sn[i] * H[(size_t)i * M + j] + I->cs[i] * H[(size_t)(i + 1) * M + j];
-          H[(size_t)i * M + j] = t;
-        }
-        const double den = std::hypot(H[(size_t)j * M + j], H[(size_t)(j + 1) * M + j]);
-        I->cs[j] = H[(size_t)j * M + j] / den;
-        I->sn[j] = H[(size_t)(j + 1) * M + j] / den;
-        H[(size_t)j * M + j] = den;
-        H[(size_t)(j + 1) * M + j] = 0.0;
-        I->g[j + 1] = -I->sn[j] * I->g[j];
-        I->g[j] = I->cs[j] * I->g[j];
-        I->cyc_conv = std::fabs(I->g[j + 1]) <= I->rtol * I->bn || I->hn == 0.0;
-        I->j = j + 1;
-        if (I->cyc_conv || I->j == M || I->iters >= I->opt.gmres_max_iters) E.push_back(k);
-        else keep.push_back(k);
-      }
-      if (E.empty()) continue;
-      // cycle end: x += M^{-1} V y, then the true residual rhs - J x -> V_0
-      rows.clear();
-      for (int k : E) {
-        BInst<T>* I = slots[k];
-        const int jj = I->j;
-        const double* H = I->H.data();
-        for (int i = jj - 1; i >= 0; --i) {
-          double t = I->g[i];
-          for (int q = i + 1; q < jj; ++q) t -= H[(size_t)i * M + q] * I->y[q];
-          I->y[i] = t / H[(size_t)i * M + i];
-        }
-        double* st = ystage + (size_t)k * 72;
-        for (int i = 0; i < jj; ++i) st[i] = I->y[i];
-        HIPCHK(c, hipMemcpyAsync(sc + (size_t)k * kScStride + kScA, st, sizeof(double) * jj, hipMemcpyHostToDevice,
-                                 c->stream));
-        rows.push_back(jj);
-        I->cycles += 1;
-      }
-      if (int rc = combine(E, rows, kScA, B_WK, B_Z, 1.0, 2)) return rc;
-      if (int rc = prec(E, B_Z, B_U)) return rc;
-      if (int rc = lin(E, B_DW, B_DW, B_U, 1.0, 1.0, 0)) return rc;
-      if (int rc = elem(1, E, B_W, B_DW, B_WK)) return rc;
-      if (int rc = lin(E, B_V0, B_RHS, B_WK, 1.0, -1.0, 0)) return rc;
-      if (int rc = vred(E, B_V0, -1, 0, kScB)) return rc;
-      if (int rc = sync()) return rc;
-      Rs.clear();
-      s.clear();
-      for (int k : E) {
-        BInst<T>* I = slots[k];
-        I->beta = std::sqrt(rd(k, kScB));
-        I->relres = I->beta / I->bn;
-        if (I->cyc_conv || I->beta <= I->rtol * I->bn || I->iters >= I->opt.gmres_max_iters) continue;
-        Rs.push_back(k);
-        s.push_back(1.0 / I->beta);
-        I->j = 0;
+      if (I->bn > 0.0) {
         std::fill(I->g.begin(), I->g.end(), 0.0);
-        I->g[0] = I->beta;
+        I->g[0] = I->bn;
+        cur.mem.push_back(k);
+        cur.jv.push_back(0);
       }
-      if (int rc = lin(Rs, B_V0, B_V0, B_V0, 0.0, 0.0, 1 | 8, &s)) return rc;
-      G = keep;
-      G.insert(G.end(), Rs.begin(), Rs.end());
-      std::sort(G.begin(), G.end());
+    }
+    cur.parity = parity;
+    if (!cur.mem.empty())
+      if (int rc = launch_tick(cur)) return rc;
+    std::vector<int> rejoin, E;
+    std::vector<char> dropped(kMaxBatch, 0);
+    while (!cur.mem.empty() || !rejoin.empty()) {
+      // issue the next step ahead of reading this one
+      nxt.mem.clear();
+      nxt.jv.clear();
+      nxt.parity = 1 - cur.parity;
+      for (size_t a = 0; a < cur.mem.size(); ++a) {
+        const BInst<T>* I = slots[cur.mem[a]];
+        if (cur.jv[a] + 2 <= M && I->iters + 2 <= I->opt.gmres_max_iters) {
+          nxt.mem.push_back(cur.mem[a]);
+          nxt.jv.push_back(cur.jv[a] + 1);
+        }
+      }
+      for (int k : rejoin) {
+        nxt.mem.push_back(k);
+        nxt.jv.push_back(0);
+      }
+      rejoin.clear();
+      if (!nxt.mem.empty()) {
+        // keep engine-slot order (instance order inside launches)
+        std::vector<size_t> ord(nxt.mem.size());
+        for (size_t a = 0; a < ord.size(); ++a) ord[a] = a;
+        std::sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return nxt.mem[x] < nxt.mem[y]; });
+        Tick sorted;
+        sorted.parity = nxt.parity;
+        for (size_t a : ord) {
+          sorted.mem.push_back(nxt.mem[a]);
+          sorted.jv.push_back(nxt.jv[a]);
+        }
+        nxt = sorted;
+        if (int rc = launch_tick(nxt)) return rc;
+      }
+      if (!cur.mem.empty()) {
+        HIPCHK(c, hipEventSynchronize(tick_ev[cur.parity]));
+        ++ticks;
+        if (timing) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, jt0[cur.parity], jt1[cur.parity]) == hipSuccess) {
+            jac_seconds += 1e-3 * ms;
+            jac_launches += 1;
+          }
+        }
+        E.clear();
+        for (size_t a = 0; a < cur.mem.size(); ++a) {
+          const int k = cur.mem[a];
+          BInst<T>* I = slots[k];
+          arnoldi_update(I, k, cur.jv[a], cur.parity);
+          if (I->cyc_conv || I->j == M || I->iters >= I->opt.gmres_max_iters) E.push_back(k);
+        }
+        if (!E.empty()) {
+          for (int k : E) dropped[k] = 1;
+          if (int rc = cycle_end(E)) return rc;
+          for (int k : E) {
+            BInst<T>* I = slots[k];
+            I->beta = rd(k, kScN + 3);
+            I->relres = I->beta / I->bn;
+            if (I->cyc_conv || I->beta <= I->rtol * I->bn || I->iters >= I->opt.gmres_max_iters) continue;
+            I->j = 0;
+            std::fill(I->g.begin(), I->g.end(), 0.0);
+            I->g[0] = I->beta;
+            rejoin.push_back(k);
+          }
+        }
+      }
+      // the issued step of an instance whose cycle ended is discarded
+      cur.mem.clear();
+      cur.jv.clear();
+      cur.parity = nxt.parity;
+      for (size_t a = 0; a < nxt.mem.size(); ++a)
+        if (!dropped[nxt.mem[a]]) {
+          cur.mem.push_back(nxt.mem[a]);
+          cur.jv.push_back(nxt.jv[a]);
+        }
+      std::fill(dropped.begin(), dropped.end(), 0);
     }
     return BSW_OK;
   }
@@ -771,7 +875,7 @@ struct EngineImpl final : EngineIf {
     int rc = bsw_mesh_upload(c, 2, r->n_vert, r->xy.data(), r->n_el, r->e2v.data(), &I->mesh);
     if (!rc) rc = bsw_disc_create(I->mesh, r->P, r->precision, &I->disc);
     if (!rc) rc = check_params(I->disc, &I->prm);
-    if (!rc) rc = e.add(I, r->W0.empty() ? nullptr : r->W0.data(), &r->ic);
+    if (!rc) rc = e.add(I, r->W0.empty() ? nullptr : r->W0.data(), 0, &r->ic);
     if (rc) {
       err = c->err;
       free_instance(I);
@@ -851,11 +955,11 @@ struct bsw_server_s {
     if (r->precision == BSW_FP64) {
       auto* x = new EngineImpl<double>();
       E.reset(x);
-      rc = x->e.init(&ictx, r->P, r->M);
+      rc = x->e.init(&ictx, 2, r->P, r->M);
     } else {
       auto* x = new EngineImpl<float>();
       E.reset(x);
-      rc = x->e.init(&ictx, r->P, r->M);
+      rc = x->e.init(&ictx, 2, r->P, r->M);
     }
     if (rc) {
       err = ictx.err;
@@ -995,7 +1099,7 @@ extern "C" {
 
 int64_t bsw_request_footprint(const bsw_solve_request* q) {
   if (!q || q->P < 1 || q->P > 3 || q->n_el < 1) return -1;
-  return instance_bytes(q->n_el, q->P, q->precision, std::max(1, std::min(64, q->opts.gmres_m)));
+  return instance_bytes(q->n_el, 2, q->P, q->precision, std::max(1, std::min(64, q->opts.gmres_m)));
 }
 
 int bsw_server_create(bsw_ctx ctx, size_t hbm_budget_bytes, int max_slots, bsw_server* out) {
@@ -1046,7 +1150,7 @@ int bsw_solve_submit(bsw_server S, const bsw_solve_request* q, uint64_t* ticket)
   r->xy.assign(q->xy, q->xy + 2 * q->n_vert);
   r->e2v.assign(q->el2vert, q->el2vert + 3 * q->n_el);
   if (q->W0) {
-    const size_t bytes = (size_t)7 * tri_np(q->P) * q->n_el * (q->precision == BSW_FP64 ? 8 : 4);
+    const size_t bytes = (size_t)7 * n_modes(2, q->P) * q->n_el * (q->precision == BSW_FP64 ? 8 : 4);
     r->W0.assign((const unsigned char*)q->W0, (const unsigned char*)q->W0 + bytes);
   }
   r->prm = q->params;
@@ -1138,3 +1242,84 @@ int bsw_server_info(bsw_server S, double* out8) {
 }
 
 }  // extern "C"
+
+// ====================================================================== whole solve of one discretisation
+namespace {
+
+// bsw_solve: the batch engine with one borrowed instance.  The engine, the
+// Krylov workspace and the reduction partials stay cached on the
+// discretisation between calls.
+template <class T>
+int solve_one(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, bsw_solve_stats* st) {
+  bsw_ctx c = d->mesh->ctx;
+  const int M = std::max(1, std::min(64, o->gmres_m));
+  auto* E = static_cast<EngineImpl<T>*>(d->eng);
+  if (!E || E->e.M != M) {
+    if (d->eng) d->eng_free(d->eng);
+    d->eng = nullptr;
+    E = new EngineImpl<T>();
+    if (int rc = E->e.init(c, d->mesh->dim, d->P, M)) {
+      delete E;
+      return rc;
+    }
+    d->eng = E;
+    d->eng_free = [](void* x) { delete static_cast<EngineImpl<T>*>(x); };
+  }
+  const int64_t len = bsw_state_len(d);
+  const size_t need = sizeof(T) * (size_t)BatchEngine<T>::ws_len(len, M);
+  if (d->gm_bytes < need) {
+    hfree(d->gm);
+    d->gm = nullptr;
+    d->gm_bytes = 0;
+    if (hipMalloc(&d->gm, need) != hipSuccess) return fail(c, BSW_E_OOM, "solver workspace");
+    d->gm_bytes = need;
+  }
+  if (int rc = ensure_part(d, (size_t)BatchEngine<T>::part_len(len, d->mesh->n_el))) return rc;
+  auto t0 = std::chrono::steady_clock::now();
+  std::memset(st, 0, sizeof(*st));
+  BInst<T>* I = new BInst<T>();
+  I->own = false;
+  I->mesh = d->mesh;
+  I->disc = d;
+  I->ws = (T*)d->gm;
+  I->part = d->part;
+  I->prm = *p;
+  I->opt = *o;
+  if (int rc = E->e.add(I, W, 1, nullptr)) {
+    delete I;
+    return rc;
+  }
+  E->e.timing = o->timing != 0;
+  E->e.jac_seconds = 0.0;
+  E->e.jac_launches = 0.0;
+  int rc = BSW_OK;
+  while (!I->finished())
+    if ((rc = E->e.step_all())) break;
+  if (!rc) {
+    hipError_t he = hipMemcpyAsync(W, I->ws + (size_t)B_W * I->ld, sizeof(T) * I->len, hipMemcpyDeviceToDevice,
+                                   c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) rc = fail(c, BSW_E_HIP, std::string("state copy: ") + hipGetErrorString(he));
+  }
+  E->e.final_stats(I);
+  *st = I->st;
+  st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  st->jac_apply_seconds = E->e.jac_seconds;
+  st->jac_apply_launches = E->e.jac_launches;
+  E->e.take(I->slot);
+  delete I;
+  return rc ? rc : st->status;
+}
+
+}  // namespace
+
+extern "C" int bsw_solve(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, void* W, bsw_solve_stats* st) {
+  if (!d || !o || !W || !st) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  if (int rc = check_params(d, p)) return rc;
+  if (o->max_newton < 1 || o->gmres_max_iters < 1 || !(o->t_end > 0))
+    return fail(d->mesh->ctx, BSW_E_ARG, "bad solve options");
+  if (!(o->dt > 0) && !(o->cfl > 0)) return fail(d->mesh->ctx, BSW_E_ARG, "need dt > 0 or cfl > 0");
+  if (d->precision == BSW_FP64) return solve_one<double>(d, p, o, (double*)W, st);
+  return solve_one<float>(d, p, o, (float*)W, st);
+}
+

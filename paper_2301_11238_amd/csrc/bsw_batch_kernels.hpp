@@ -21,9 +21,13 @@
 namespace bsw {
 
 constexpr int kMaxBatch = 128;  // instances per batch
-constexpr int kVT = 2048;       // reals per vector tile (256 lanes x 8)
-constexpr int kScStride = 144;  // FP64 scalars per instance: two rows of 72
-constexpr int kScA = 0, kScB = 72;
+constexpr int kVT = 512;        // reals per vector tile (256 lanes x 2)
+// FP64 scalars per instance (device array and a host-mapped mirror):
+// Gram-Schmidt coefficient rows of even and odd Arnoldi steps, the scales of
+// the stored Krylov vectors, the Krylov combination weights and norms.
+constexpr int kScStride = 448;
+constexpr int kScA = 0, kScB = 72, kScA1 = 144, kScB1 = 216;
+constexpr int kScS = 288, kScY = 360, kScN = 432;
 constexpr int kSlotJ = 1 << 16;  // slot flag: add the instance's Krylov index
 
 struct BatchSet {
@@ -51,7 +55,7 @@ struct InstDesc {
   T* ws;            // state vectors: slot k starts at ws + k * ld
   int64_t ld;
   int64_t len;      // n_f N_p n_el
-  T* blk;           // block-Jacobi inverses, [row][col][n_el]
+  float* blk;       // block-Jacobi inverses (FP32), [row][col][n_el]
   T* blk_raw;       // diagonal blocks, [n_el][row][col]
   T* trL;           // face traces of the linearisation state
   T* trA;           // face traces of the last residual argument
@@ -93,14 +97,16 @@ __global__ void __launch_bounds__(256) kb_step_begin(const InstDesc<T>* __restri
   if (e < I.m.n_el) step_begin_elem<D, P, T>(bslot(I, sW, 0), bslot(I, sB, 0), I.m, I.p, e);
 }
 
-// face traces of slot sX into trL (which 0), trA (1) or trX (2); 256 elements per tile
+// face traces of slot sX into trL (which 0), trA (1) or trX (2); tiles of
+// 256 (field, face, element) items
 template <int D, int P, class T>
 __global__ void __launch_bounds__(256) kb_trace(const InstDesc<T>* __restrict__ ds, BatchSet A, int sX, int which) {
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
-  const int e = (blockIdx.x - A.tile0[ai]) * 256 + threadIdx.x;
+  const int64_t item = (int64_t)(blockIdx.x - A.tile0[ai]) * 256 + threadIdx.x;
   T* tr = which == 0 ? I.trL : (which == 1 ? I.trA : I.trX);
-  if (e < I.m.n_el) trace_elem<D, P, T>(bslot(I, sX, A.jv[ai]), tr, I.m.n_el, e);
+  if (item < (int64_t)Shape<D, P>::NF * Shape<D, P>::NFC * I.m.n_el)
+    trace_item<D, P, T>(bslot(I, sX, A.jv[ai]), tr, I.m.n_el, item);
 }
 
 // MODE 0: R = residual(W; b_old) with the traces in trA; MODE 1: y = J(W) x
@@ -126,7 +132,7 @@ __global__ void __launch_bounds__(128) kb_jac_columns(const InstDesc<T>* __restr
 }
 
 template <int BS, class T>
-__global__ void __launch_bounds__(64) kb_block_inverse(const InstDesc<T>* __restrict__ ds, BatchSet A) {
+__global__ void __launch_bounds__(inv_threads<BS>()) kb_block_inverse(const InstDesc<T>* __restrict__ ds, BatchSet A) {
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
   block_inverse_elem<BS, T>(I.blk_raw, I.blk, I.m.n_el, blockIdx.x - A.tile0[ai]);
@@ -186,7 +192,7 @@ __global__ void __launch_bounds__(256) kb_lin(const InstDesc<T>* __restrict__ ds
 
 // y = s (w - sum_{i < rows} c_i V_i) with c in the instance's scalar row
 // `coff`; flag 1: s = per-instance scalar (else 1), 2: no w term (y = sum),
-// 4: y += (instead of =) the combination, with sign sgn
+// 4: y += (instead of =) the combination, with sign sgn, 8: c_i sigma_i
 template <class T>
 __global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict__ ds, BatchSet A, const double* sc,
                                                    int coff, int sV0, int sw, int sy, double sgn, int flags) {
@@ -197,6 +203,7 @@ __global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict_
   const int rows = A.rows[ai];
   const double s = (flags & 1) ? A.s[ai] : 1.0;
   const double* c = sc + (int64_t)slot * kScStride + coff;
+  const double* sg = sc + (int64_t)slot * kScStride + kScS;
   const T* V = bslot(I, sV0, j);
   const T* w = bslot(I, sw, j);
   T* y = bslot(I, sy, j);
@@ -206,37 +213,184 @@ __global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict_
     const int64_t i = i0 + k * 256;
     if (i >= I.len) break;
     double acc = 0.0;
-    for (int r = 0; r < rows; ++r) acc += c[r] * (double)V[(int64_t)r * I.ld + i];
+    if (flags & 8)
+      for (int r = 0; r < rows; ++r) acc += c[r] * sg[r] * (double)V[(int64_t)r * I.ld + i];
+    else
+      for (int r = 0; r < rows; ++r) acc += c[r] * (double)V[(int64_t)r * I.ld + i];
     if (flags & 4) y[i] = (T)((double)y[i] + sgn * acc);
     else if (flags & 2) y[i] = (T)(s * acc);
     else y[i] = (T)(s * ((double)w[i] - acc));
   }
 }
 
-// ------------------------------------------------------------------ per-instance reductions
-// partials of V_r . w for r < rows (and w . w as the last row when self)
-template <class T>
-__global__ void __launch_bounds__(256) kb_multidot(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0, int sw,
-                                                    int self) {
-  const int ai = bset_find(A, blockIdx.x);
-  const InstDesc<T> I = ds[A.inst[ai]];
-  const int rows = A.rows[ai];
-  const int r = blockIdx.y;
-  if (r >= rows) return;
-  const int t = blockIdx.x - A.tile0[ai];
-  const T* w = bslot(I, sw, 0);
-  const T* v = (self && r == rows - 1) ? w : bslot(I, sV0, 0) + (int64_t)r * I.ld;
-  double acc = 0.0;
-  const int64_t i0 = (int64_t)t * kVT + threadIdx.x;
+// ------------------------------------------------------------------ Krylov (Arnoldi) stages
+// The Krylov vectors are stored unnormalised: V_true[r] = sigma_r V[r] with
+// sigma_r = sc[kScS + r], so each new vector's norm is computed exactly from
+// the vector itself and no pass only rescales.
+
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-  for (int k = 0; k < kVT / 256; ++k) {
-    const int64_t i = i0 + k * 256;
-    if (i < I.len) acc += (double)v[i] * (double)w[i];
-  }
-  const double x = bred(acc, 0);
-  if (threadIdx.x == 0) I.part[(int64_t)r * I.ntile + t] = x;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
+// per-tile partials of rows r: V_r . w (r < rows, or r < rows - 1 and the last
+// row w . w when self); four wave sums per row combined in a fixed order
+template <class T>
+__device__ __forceinline__ void tile_dots(const InstDesc<T>& I, const T* __restrict__ V, double w0, double w1,
+                                          int64_t i0, int rows, int self, int t) {
+  __shared__ double sh[72][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i1 = i0 + 256;
+  const int nv = self ? rows - 1 : rows;  // rows against stored vectors
+  const bool in0 = i0 < I.len, in1 = i1 < I.len;
+  // eight rows at a time: sixteen independent loads in flight per lane
+  for (int r0 = 0; r0 < rows; r0 += 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = r0 + u;
+      a[u] = 0.0;
+      if (r < nv) {
+        const T* v = V + (int64_t)r * I.ld;
+        a[u] = (in0 ? (double)v[i0] * w0 : 0.0) + (in1 ? (double)v[i1] * w1 : 0.0);
+      } else if (r < rows) {
+        a[u] = w0 * w0 + w1 * w1;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = wave_sum(a[u]);
+    if (lane == 0)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (r0 + u < rows) sh[r0 + u][wv] = a[u];
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < rows; r += 256) I.part[(int64_t)r * I.ntile + t] = (sh[r][0] + sh[r][1]) + (sh[r][2] + sh[r][3]);
+}
+
+// Gram-Schmidt pass 1: partials of V_r . w, r <= j
+template <class T>
+__global__ void __launch_bounds__(256) kb_dots(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0, int sw) {
+  const int ai = bset_find(A, blockIdx.x);
+  const InstDesc<T> I = ds[A.inst[ai]];
+  const int t = blockIdx.x - A.tile0[ai];
+  const T* w = bslot(I, sw, 0);
+  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
+  const double w0 = i0 < I.len ? (double)w[i0] : 0.0, w1 = i1 < I.len ? (double)w[i1] : 0.0;
+  tile_dots<T>(I, bslot(I, sV0, 0), w0, w1, i0, A.jv[ai] + 1, 0, t);
+}
+
+// w <- w - sum_{r <= j} h_r sigma_r V_r (h in row coff), then the partials of
+// V_r . w (r <= j) and w . w: the subtraction of pass 1 and the dots of pass 2
+template <class T>
+__global__ void __launch_bounds__(256) kb_axpy_dots(const InstDesc<T>* __restrict__ ds, BatchSet A,
+                                                     const double* __restrict__ sc, int coff, int sV0, int sw) {
+  const int ai = bset_find(A, blockIdx.x);
+  const int slot = A.inst[ai];
+  const InstDesc<T> I = ds[slot];
+  const int t = blockIdx.x - A.tile0[ai];
+  const int rows = A.jv[ai] + 1;
+  const double* h = sc + (int64_t)slot * kScStride + coff;
+  const double* sg = sc + (int64_t)slot * kScStride + kScS;
+  const T* V = bslot(I, sV0, 0);
+  T* w = bslot(I, sw, 0);
+  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
+  double a0 = i0 < I.len ? (double)w[i0] : 0.0, a1 = i1 < I.len ? (double)w[i1] : 0.0;
+  {
+    const bool in0 = i0 < I.len, in1 = i1 < I.len;
+    for (int r0 = 0; r0 < rows; r0 += 8) {
+      double v0[8], v1[8], c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = r0 + u;
+        const T* v = V + (int64_t)r * I.ld;
+        const bool ok = r < rows;
+        c[u] = ok ? h[r] * sg[r] : 0.0;
+        v0[u] = ok && in0 ? (double)v[i0] : 0.0;
+        v1[u] = ok && in1 ? (double)v[i1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0 -= c[u] * v0[u];
+        a1 -= c[u] * v1[u];
+      }
+    }
+  }
+  if (i0 < I.len) w[i0] = (T)a0;
+  if (i1 < I.len) w[i1] = (T)a1;
+  // the dots use the stored (rounded) values
+  a0 = i0 < I.len ? (double)(T)a0 : 0.0;
+  a1 = i1 < I.len ? (double)(T)a1 : 0.0;
+  tile_dots<T>(I, V, a0, a1, i0, rows + 1, 1, t);
+}
+
+// V_{j+1} <- w - sum_{r <= j} h_r sigma_r V_r (h in row coff), unnormalised,
+// and the partials of its squared norm
+template <class T>
+__global__ void __launch_bounds__(256) kb_normalize(const InstDesc<T>* __restrict__ ds, BatchSet A,
+                                                     const double* __restrict__ sc, int coff, int sV0, int sw) {
+  const int ai = bset_find(A, blockIdx.x);
+  const int slot = A.inst[ai];
+  const InstDesc<T> I = ds[slot];
+  const int t = blockIdx.x - A.tile0[ai];
+  const int rows = A.jv[ai] + 1;
+  const double* h = sc + (int64_t)slot * kScStride + coff;
+  const double* sg = sc + (int64_t)slot * kScStride + kScS;
+  const T* V = bslot(I, sV0, 0);
+  const T* w = bslot(I, sw, 0);
+  T* y = bslot(I, sV0, 0) + (int64_t)rows * I.ld;
+  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
+  double a0 = i0 < I.len ? (double)w[i0] : 0.0, a1 = i1 < I.len ? (double)w[i1] : 0.0;
+  {
+    const bool in0 = i0 < I.len, in1 = i1 < I.len;
+    for (int r0 = 0; r0 < rows; r0 += 8) {
+      double v0[8], v1[8], c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = r0 + u;
+        const T* v = V + (int64_t)r * I.ld;
+        const bool ok = r < rows;
+        c[u] = ok ? h[r] * sg[r] : 0.0;
+        v0[u] = ok && in0 ? (double)v[i0] : 0.0;
+        v1[u] = ok && in1 ? (double)v[i1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0 -= c[u] * v0[u];
+        a1 -= c[u] * v1[u];
+      }
+    }
+  }
+  double q = 0.0;
+  if (i0 < I.len) { const T u = (T)a0; y[i0] = u; q += (double)u * (double)u; }
+  if (i1 < I.len) { const T u = (T)a1; y[i1] = u; q += (double)u * (double)u; }
+  const double x = bred(q, 0);
+  if (threadIdx.x == 0) I.part[t] = x;
+}
+
+// z = sigma_j M^{-1} V_j (the preconditioner on the stored Krylov vector j)
+template <int BS, class T>
+__global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restrict__ ds, BatchSet A,
+                                                       const double* __restrict__ sc, int sV0, int sZ) {
+  const int ai = bset_find(A, blockIdx.x);
+  const int slot = A.inst[ai];
+  const InstDesc<T> I = ds[slot];
+  const int j = A.jv[ai];
+  const int n = I.m.n_el;
+  const int64_t idx = (int64_t)(blockIdx.x - A.tile0[ai]) * 256 + threadIdx.x;
+  if (idx >= (int64_t)BS * n) return;
+  const double sgm = sc[(int64_t)slot * kScStride + kScS + j];
+  const int row = (int)(idx / n), e = (int)(idx % n);
+  const T* x = bslot(I, sV0, 0) + (int64_t)j * I.ld;
+  const float* Ai = I.blk + (size_t)row * BS * n + e;
+  double s = 0.0;
+#pragma unroll 7
+  for (int c = 0; c < BS; ++c) s += (double)Ai[(size_t)c * n] * (double)x[(size_t)c * n + e];
+  bslot(I, sZ, 0)[(size_t)row * n + e] = (T)(sgm * s);
+}
+
+// ------------------------------------------------------------------ per-instance reductions
 // partials of sum x^2 (op 0) or max |x| (op 1) over up to two slots
 template <class T>
 __global__ void __launch_bounds__(256) kb_vred(const InstDesc<T>* __restrict__ ds, BatchSet A, int s0, int s1,
@@ -262,9 +416,13 @@ __global__ void __launch_bounds__(256) kb_vred(const InstDesc<T>* __restrict__ d
 
 // final pass: one workgroup per (instance, row) folds the instance's partials
 // in a fixed order; op of row r is bits 2r..2r+1 of ops (0 sum, 1 max, 2 min)
+// scl: rows r <= j are multiplied by sigma_r (dots against stored Krylov
+// vectors); sig >= 0: row 0 is a sum of squares, its square root is written
+// and sigma_{j + sig} = 1 / root (0 for a zero vector)
 template <class T>
 __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restrict__ ds, BatchSet A, int etile,
-                                                      unsigned ops, double* sc, double* sch, int off) {
+                                                      unsigned ops, double* sc, double* sch, int off, int scl,
+                                                      int sig) {
   const int ai = blockIdx.x;
   const int slot = A.inst[ai];
   const InstDesc<T> I = ds[slot];
@@ -277,10 +435,21 @@ __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restri
     const double v = I.part[(int64_t)r * nt + t];
     acc = op == 0 ? acc + v : (op == 1 ? fmax(acc, v) : fmin(acc, v));
   }
-  const double x = bred(acc, op);
+  double x = bred(acc, op);
   if (threadIdx.x == 0) {
-    sc[(int64_t)slot * kScStride + off + r] = x;
-    sch[(int64_t)slot * kScStride + off + r] = x;
+    double* s = sc + (int64_t)slot * kScStride;
+    double* sh = sch + (int64_t)slot * kScStride;
+    const int j = A.jv[ai];
+    if (sig >= 0) {
+      x = sqrt(x);
+      const double inv = x > 0.0 ? 1.0 / x : 0.0;
+      s[kScS + j + sig] = inv;
+      sh[kScS + j + sig] = inv;
+    } else if (scl && r <= j) {
+      x *= s[kScS + r];
+    }
+    s[off + r] = x;
+    sh[off + r] = x;
   }
 }
 

@@ -41,30 +41,31 @@ __device__ __forceinline__ void interp(const T (&phi)[Shape<D, P>::NP], const T 
 // tr[(f * NFP + kp) * n + e] with kp = face * NFQ + point.  One coalesced pass
 // per state; an element then reads its neighbour's side of a shared face
 // point as NF loads instead of interpolating NF x NP neighbour coefficients.
+// one item: field f on face fc of element e, item = (f * NFC + fc) * n + e
 template <int D, int P, class T>
-__device__ __forceinline__ void trace_elem(const T* __restrict__ X, T* __restrict__ tr, int n, int e) {
+__device__ __forceinline__ void trace_item(const T* __restrict__ X, T* __restrict__ tr, int n, int64_t item) {
   using S = Shape<D, P>;
   const Tab<D, P, T>& tb = tab<D, P, T>();
   constexpr int NFP = S::NFC * S::NFQ;
-#pragma unroll 1
-  for (int f = 0; f < S::NF; ++f) {
-    T c[S::NP];
+  const int e = (int)(item % n);
+  const int ff = (int)(item / n);
+  const int f = ff / S::NFC, fc = ff % S::NFC;
+  T c[S::NP];
 #pragma unroll
-    for (int i = 0; i < S::NP; ++i) c[i] = X[(size_t)(f * S::NP + i) * n + e];
+  for (int i = 0; i < S::NP; ++i) c[i] = X[(size_t)(f * S::NP + i) * n + e];
 #pragma unroll
-    for (int kp = 0; kp < NFP; ++kp) {
-      T s = T(0);
+  for (int r = 0; r < S::NFQ; ++r) {
+    T s = T(0);
 #pragma unroll
-      for (int i = 0; i < S::NP; ++i) s += tb.fphi[kp / S::NFQ][kp % S::NFQ][i] * c[i];
-      tr[(size_t)(f * NFP + kp) * n + e] = s;
-    }
+    for (int i = 0; i < S::NP; ++i) s += tb.fphi[fc][r][i] * c[i];
+    tr[(size_t)(f * NFP + fc * S::NFQ + r) * n + e] = s;
   }
 }
 
 template <int D, int P, class T>
 __global__ void __launch_bounds__(256) k_trace(const T* __restrict__ X, T* __restrict__ tr, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) trace_elem<D, P, T>(X, tr, n, e);
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item < (int64_t)Shape<D, P>::NF * Shape<D, P>::NFC * n) trace_item<D, P, T>(X, tr, n, item);
 }
 
 // the neighbour's values at its local face g, point rr (points run in the
@@ -616,112 +617,123 @@ __global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, co
   jac_columns_elem<D, P, T>(W, trW, blocks, m, p, blockIdx.x);
 }
 
-// Inverse of one diagonal block per workgroup (one wavefront): LU with
-// partial pivoting staged in LDS (lanes own rows for the pivot search and the
-// elimination), then lane k solves L U y = P e_k for column k of the inverse.
+// Inverse of one diagonal block per workgroup: LU with partial pivoting, then
+// lane k solves L U y = P e_k for column k of the inverse.  Each lane keeps
+// one row of the block in registers through the elimination; the pivot row of
+// a step goes through LDS once and every other lane reads it as a broadcast,
+// so the elimination runs on registers.  Rows are not swapped: a lane that
+// supplied the pivot of step k holds row k of the factors, pr[k] its
+// original index.  The LU factors then go to LDS in pivot order for the
+// column solves (uniform, broadcast reads).
 // The inverse is written element-fastest, Ainv[(row * BS + col) * n + e], so
-// the preconditioner apply is a coalesced batched mat-vec.
+// the preconditioner apply is a coalesced batched mat-vec.  It is stored in
+// FP32 for both state precisions: the preconditioner only steers GMRES (the
+// Krylov residual uses the exact Jacobian), and its apply reads half the bytes.
+template <int BS>
+constexpr int inv_threads() { return 64 * ((BS + 63) / 64); }
+
 template <int BS, class T>
-__device__ __forceinline__ void block_inverse_elem(const T* __restrict__ A, T* __restrict__ Ainv, int n, int e) {
+__device__ __forceinline__ void block_inverse_elem(const T* __restrict__ A, float* __restrict__ Ainv, int n, int e) {
   constexpr int LD = BS + 1;
-  constexpr int RPL = (BS + 63) / 64;  // rows per lane
+  constexpr int NT = inv_threads<BS>();
+  constexpr int NW = NT / 64;
   __shared__ T a[BS * LD];
+  __shared__ T prow[BS];
   __shared__ int pr[BS];
-  __shared__ int piv_s;
-  const int lane = threadIdx.x;
+  __shared__ T wbest[NW];
+  __shared__ int wbi[NW];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const bool own = t < BS;
   const T* src = A + (size_t)e * BS * BS;
-  for (int idx = lane; idx < BS * BS; idx += 64) a[(idx / BS) * LD + idx % BS] = src[idx];
-  for (int r = lane; r < BS; r += 64) pr[r] = r;
-  __syncthreads();
-  for (int k = 0; k < BS; ++k) {
-    // pivot: largest |a[i][k]|, i >= k (lowest index on ties)
-    T best = T(-1);
-    int bi = k;
+  T r[BS];
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int i = lane + 64 * t;
-      if (i >= k && i < BS) {
-        const T v = fabs(a[i * LD + k]);
-        if (v > best) { best = v; bi = i; }
-      }
-    }
+  for (int j = 0; j < BS; ++j) r[j] = own ? src[(size_t)t * BS + j] : T(0);
+  bool done = !own;
+  int myk = 0;
+#pragma unroll
+  for (int k = 0; k < BS; ++k) {
+    // pivot: largest |a[i][k]| over the rows not yet used (lowest row on ties)
+    T best = done ? T(-1) : fabs(r[k]);
+    int bi = t;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const T ob = __shfl_xor(best, off);
       const int oi = __shfl_xor(bi, off);
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    if (lane == 0) piv_s = bi;
-    __syncthreads();
-    const int pv = piv_s;
-    if (pv != k) {
-      for (int j = lane; j < BS; j += 64) {
-        const T t = a[k * LD + j];
-        a[k * LD + j] = a[pv * LD + j];
-        a[pv * LD + j] = t;
-      }
-      if (lane == 0) {
-        const int t = pr[k];
-        pr[k] = pr[pv];
-        pr[pv] = t;
-      }
+    if constexpr (NW > 1) {
+      if (lane == 0) { wbest[wv] = best; wbi[wv] = bi; }
+      __syncthreads();
+      best = wbest[0];
+      bi = wbi[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w)
+        if (wbest[w] > best || (wbest[w] == best && wbi[w] < bi)) { best = wbest[w]; bi = wbi[w]; }
+    }
+    if (t == bi) {
+#pragma unroll
+      for (int j = k; j < BS; ++j) prow[j] = r[j];
+      pr[k] = t;
+      myk = k;
+      done = true;
     }
     __syncthreads();
-    const T inv = T(1) / a[k * LD + k];
+    if (!done) {
+      const T l = r[k] / prow[k];
+      r[k] = l;
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int i = lane + 64 * t;
-      if (i > k && i < BS) {
-        const T l = a[i * LD + k] * inv;
-        a[i * LD + k] = l;
-        for (int j = k + 1; j < BS; ++j) a[i * LD + j] -= l * a[k * LD + j];
-      }
+      for (int j = k + 1; j < BS; ++j) r[j] -= l * prow[j];
     }
     __syncthreads();
   }
+  if (own)
+#pragma unroll
+    for (int j = 0; j < BS; ++j) a[myk * LD + j] = r[j];
+  __syncthreads();
   // columns of the inverse: A^{-1} e_k = U^{-1} L^{-1} P e_k, (P e_k)[r] = [pr[r] == k]
-  for (int k = lane; k < BS; k += 64) {
+  for (int k = t; k < BS; k += NT) {
     T y[BS];
 #pragma unroll
-    for (int r = 0; r < BS; ++r) y[r] = pr[r] == k ? T(1) : T(0);
+    for (int r2 = 0; r2 < BS; ++r2) y[r2] = pr[r2] == k ? T(1) : T(0);
 #pragma unroll
-    for (int r = 1; r < BS; ++r) {
-      T s = y[r];
+    for (int r2 = 1; r2 < BS; ++r2) {
+      T s2 = y[r2];
 #pragma unroll
-      for (int c = 0; c < r; ++c) s -= a[r * LD + c] * y[c];
-      y[r] = s;
+      for (int c = 0; c < r2; ++c) s2 -= a[r2 * LD + c] * y[c];
+      y[r2] = s2;
     }
 #pragma unroll
-    for (int r = BS - 1; r >= 0; --r) {
-      T s = y[r];
+    for (int r2 = BS - 1; r2 >= 0; --r2) {
+      T s2 = y[r2];
 #pragma unroll
-      for (int c = r + 1; c < BS; ++c) s -= a[r * LD + c] * y[c];
-      y[r] = s / a[r * LD + r];
+      for (int c = r2 + 1; c < BS; ++c) s2 -= a[r2 * LD + c] * y[c];
+      y[r2] = s2 / a[r2 * LD + r2];
     }
 #pragma unroll
-    for (int r = 0; r < BS; ++r) Ainv[((size_t)r * BS + k) * n + e] = y[r];
+    for (int r2 = 0; r2 < BS; ++r2) Ainv[((size_t)r2 * BS + k) * n + e] = (float)y[r2];
   }
 }
 
 template <int BS, class T>
-__global__ void __launch_bounds__(64) k_block_inverse(const T* __restrict__ A, T* __restrict__ Ainv, int n) {
+__global__ void __launch_bounds__(inv_threads<BS>()) k_block_inverse(const T* __restrict__ A, float* __restrict__ Ainv,
+                                                                     int n) {
   block_inverse_elem<BS, T>(A, Ainv, n, blockIdx.x);
 }
 
 // y = blockdiag(A_e)^{-1} x: one lane per (row, element), element fastest.
 template <int BS, class T>
-__device__ __forceinline__ void block_apply_item(const T* __restrict__ Ainv, const T* __restrict__ x,
+__device__ __forceinline__ void block_apply_item(const float* __restrict__ Ainv, const T* __restrict__ x,
                                                  T* __restrict__ y, int n, int64_t idx) {
   const int row = (int)(idx / n), e = (int)(idx % n);
-  const T* arow = Ainv + (size_t)row * BS * n + e;
+  const float* arow = Ainv + (size_t)row * BS * n + e;
   T s = T(0);
 #pragma unroll
-  for (int j = 0; j < BS; ++j) s += arow[(size_t)j * n] * x[(size_t)j * n + e];
+  for (int j = 0; j < BS; ++j) s += (T)arow[(size_t)j * n] * x[(size_t)j * n + e];
   y[(size_t)row * n + e] = s;
 }
 
 template <int BS, class T>
-__global__ void __launch_bounds__(256) k_block_apply(const T* __restrict__ Ainv, const T* __restrict__ x,
+__global__ void __launch_bounds__(256) k_block_apply(const float* __restrict__ Ainv, const T* __restrict__ x,
                                                       T* __restrict__ y, int n) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (int64_t)BS * n) block_apply_item<BS, T>(Ainv, x, y, n, idx);

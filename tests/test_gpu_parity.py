@@ -107,13 +107,19 @@ def test_jacobian_apply_blocks_and_preconditioner(ctx, dim, P, n, reg):
     Bg = pr.host(pr.disc.jacobian_blocks())
     Bo = pr.orc.jac_blocks(p, W, dt)
     assert np.abs(Bg - Bo).max() <= 1e-12 * np.abs(Bo).max()
-    # preconditioner: block_e y_e = x_e
+    # preconditioner: the block inverses are stored in FP32, so y_e is the
+    # exact block solve up to the rounding of each inverse entry:
+    # |y - B^{-1} x| <= 2^-24 |B^{-1}| |x| (+ FP64 inversion error)
     yp = pr.host(pr.disc.precond_apply(pr.dev(x)))
     nf, np_, ne = pr.shape
     xe = np.transpose(x, (2, 0, 1)).reshape(ne, nf * np_)
     ye = np.transpose(yp, (2, 0, 1)).reshape(ne, nf * np_)
-    res = np.einsum("eij,ej->ei", Bo, ye) - xe
-    assert np.abs(res).max() <= 1e-10 * np.abs(xe).max()
+    Binv = np.linalg.inv(Bo)
+    ex = np.einsum("eij,ej->ei", Binv, xe)
+    bound = 2.0 ** -23 * np.einsum("eij,ej->ei", np.abs(Binv), np.abs(xe)) + 1e-9 * np.abs(ex).max()
+    assert np.all(np.abs(ye - ex) <= bound)
+    # and not much looser than that: the rounding is visible but small
+    assert np.abs(ye - ex).max() <= 1e-5 * np.abs(ex).max()
 
 
 def test_stage_update_and_reductions(ctx):
