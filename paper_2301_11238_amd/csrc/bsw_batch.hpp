@@ -442,7 +442,8 @@ struct BatchEngine {
   // twice, per instance: J x = rhs to ||rhs - J x|| <= rtol ||rhs|| with
   // x = B_DW starting at 0.  One Arnoldi step of every participating instance
   // is nine launches (preconditioner, traces, Jacobian, dots, fused
-  // subtraction and dots, new vector and its norm, three folds); the
+  // subtraction and dots, new vector and its norm, and a fold kernel after
+  // each of the three reductions); the
   // Hessenberg column, Givens rotations and the cycle test run on the host
   // from the mapped scalars.  The host issues step t+1 before it reads step
   // t (Krylov index and iteration cap known in advance), so the device never

@@ -228,45 +228,42 @@ __global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict_
 // sigma_r = sc[kScS + r], so each new vector's norm is computed exactly from
 // the vector itself and no pass only rescales.
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
 
 // per-tile partials of rows r: V_r . w (r < rows, or r < rows - 1 and the last
-// row w . w when self); four wave sums per row combined in a fixed order
+// row w . w when self).  Eight rows at a time: every lane forms its two-term
+// products (sixteen independent loads in flight), the 8 x 256 products are
+// transposed through LDS, 32 lanes per row add eight each and a 32-lane
+// butterfly finishes the row -- a fixed summation order.
 template <class T>
 __device__ __forceinline__ void tile_dots(const InstDesc<T>& I, const T* __restrict__ V, double w0, double w1,
                                           int64_t i0, int rows, int self, int t) {
-  __shared__ double sh[72][4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double red[8][257];
   const int64_t i1 = i0 + 256;
   const int nv = self ? rows - 1 : rows;  // rows against stored vectors
   const bool in0 = i0 < I.len, in1 = i1 < I.len;
-  // eight rows at a time: sixteen independent loads in flight per lane
+  const int tid = threadIdx.x, ru = tid >> 5, rl = tid & 31;
   for (int r0 = 0; r0 < rows; r0 += 8) {
-    double a[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int r = r0 + u;
-      a[u] = 0.0;
+      double a = 0.0;
       if (r < nv) {
         const T* v = V + (int64_t)r * I.ld;
-        a[u] = (in0 ? (double)v[i0] * w0 : 0.0) + (in1 ? (double)v[i1] * w1 : 0.0);
+        a = (in0 ? (double)v[i0] * w0 : 0.0) + (in1 ? (double)v[i1] * w1 : 0.0);
       } else if (r < rows) {
-        a[u] = w0 * w0 + w1 * w1;
+        a = w0 * w0 + w1 * w1;
       }
+      red[u][tid] = a;
     }
+    __syncthreads();
+    double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = wave_sum(a[u]);
-    if (lane == 0)
+    for (int m = 0; m < 8; ++m) s += red[ru][rl * 8 + m];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (r0 + u < rows) sh[r0 + u][wv] = a[u];
+    for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (rl == 0 && r0 + ru < rows) I.part[(int64_t)(r0 + ru) * I.ntile + t] = s;
+    __syncthreads();
   }
-  __syncthreads();
-  for (int r = threadIdx.x; r < rows; r += 256) I.part[(int64_t)r * I.ntile + t] = (sh[r][0] + sh[r][1]) + (sh[r][2] + sh[r][3]);
 }
 
 // Gram-Schmidt pass 1: partials of V_r . w, r <= j

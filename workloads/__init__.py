@@ -255,6 +255,35 @@ def config4_instance(k: int, seed: int = 4, n_range=(500.0, 50000.0)) -> Problem
                    {"reg": reg, "eps": eps, "N": N, "k": k})
 
 
+# Served requests: slope flows (the incline configuration's physics) of mixed
+# mesh size, order and Bingham parameters, and dam breaks limited to
+# eps >= 1e-3.  Ensemble draws with smaller eps cap the Newton iteration of the
+# method itself (exact linear solves included), so their results carry no
+# accuracy to compare.
+def serving_request(k: int, seed: int = 6, n_range=(512.0, 8192.0)) -> Problem:
+    rng = rng_for(seed, 40, k)
+    n = math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))
+    N = mesh_side_for_count(n)
+    P = int(rng.integers(1, 4))
+    reg = int(rng.integers(1, 4))
+    eps = math.exp(rng.uniform(math.log(1e-3), math.log(1e-2)))
+    eta = float(rng.uniform(0.5, 2.0))
+    mesh_seed = int(rng.integers(0, 2**31 - 1))
+    xy, e2v = mesh_tri(N, 20.0, 20.0, 0.1, mesh_seed)
+    if rng.uniform() < 0.5:
+        sigma0 = float(rng.uniform(20.0, 200.0))
+        prm = Params.from_eps(eps, g=9.81, rho=1000.0, alpha=math.atan(0.1), eta=eta, sigma0=sigma0, reg=reg)
+        ic = IC(kind=IC_MOUND, a=1.0, b=float(rng.uniform(0.2, 0.8)), x0=10.0, y0=10.0, d=4.0)
+        kind = "slope"
+    else:
+        sigma0 = float(rng.uniform(10.0, 100.0))
+        prm = Params.from_eps(eps, g=9.81, rho=1000.0, alpha=0.0, eta=eta, sigma0=sigma0, reg=reg)
+        ic = IC(kind=IC_DISK, a=0.5 + float(rng.uniform(0.5, 1.5)), b=0.5, x0=10.0, y0=10.0, r=2.5)
+        kind = "dambreak"
+    return Problem(f"served_{kind}_{k}", 2, P, xy, e2v, prm, ic, 1.0, 0.2, BC_WALL,
+                   {"reg": reg, "eps": eps, "N": N, "k": k, "kind": kind})
+
+
 def config4(n_inst: int = 512, seed: int = 4):
     return [config4_instance(k, seed) for k in range(n_inst)]
 
