@@ -97,10 +97,17 @@ typedef struct {
   double newton_tol;       /* stop when ||dW||_inf <= newton_tol (1 + ||W||_inf) */
   double gmres_rtol;       /* tightest relative residual asked of GMRES; each Newton
                               system uses an Eisenstat-Walker forcing term in
-                              [gmres_rtol, 1e-3] */
+                              [gmres_rtol, forcing_max] */
   double cfl, t_end, dt;
   int32_t max_steps;       /* < 0: all steps */
   int32_t timing;          /* nonzero: time every Jacobian-apply launch with HIP events */
+  double forcing_max;      /* largest GMRES relative tolerance of a Newton system (the
+                              forcing term's ceiling); <= 0 selects 1e-2 */
+  int32_t cont_steps;      /* continuation on gamma (Sec. 6.3): n >= 2 Newton solves per
+                              time step at gamma_i = cont_gamma0 + (i-1)(gamma -
+                              cont_gamma0)/(n-1), each starting from the last; beta and
+                              the other parameters stay.  < 2: one solve at gamma */
+  double cont_gamma0;      /* first gamma of the continuation (> 0 when cont_steps >= 2) */
 } bsw_solve_opts;
 
 typedef struct {
@@ -196,7 +203,9 @@ int bsw_cfl_dt(bsw_disc disc, const bsw_params* prm, const void* W, double cfl, 
 /* Backward-Euler time loop from the state in W (device, updated in place) to
  * opts->t_end: per step b_old, then inexact Newton (residual, linearize,
  * block-Jacobi GMRES for Eq. Newton, backtracking on ||R||, update) until
- * ||dW||_inf <= newton_tol (1 + ||W||_inf) or max_newton iterations.
+ * ||dW||_inf <= newton_tol (1 + ||W||_inf) or max_newton iterations (per
+ * continuation stage when cont_steps >= 2).  A step counts as capped when its
+ * last Newton solve (at the target gamma) hit the cap.
  * Returns BSW_W_NOT_CONVERGED if any step hit the cap. */
 int bsw_solve(bsw_disc disc, const bsw_params* prm, const bsw_solve_opts* opts, void* W,
               bsw_solve_stats* stats_out);

@@ -10,6 +10,7 @@ side works per element ([n_el, n_f, N_p]) and this wrapper transposes.
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import math
 import os
 import subprocess
@@ -153,6 +154,10 @@ class SolveOptions:
     t_end: float = 1.0
     dt_override: float = 0.0
     max_steps: int = -1
+    # continuation on gamma (Sec. 6.3): n >= 2 Newton solves per time step at
+    # gamma_i = gamma0 + (i - 1) (gamma - gamma0) / (n - 1), each from the last
+    cont_steps: int = 0
+    cont_gamma0: float = 0.0
 
 
 class Oracle:
@@ -349,10 +354,24 @@ class Oracle:
                   mass0=float(diag[0]), mass_end=0.0, max_mass_drift=0.0, active_pct=0.0, t_end=0.0)
         t = 0.0
         be = np.zeros_like(We)
+        # continuation on gamma (Sec. 6.3): the regularisation parameter of the
+        # i-th Newton solve of a step; beta and every other parameter stay
+        if opts.cont_steps >= 2:
+            n = opts.cont_steps
+            g0, g1 = float(opts.cont_gamma0), float(params.gamma)
+            stages = [make_params(dataclasses.replace(params, gamma=g0 + (i - 1) * (g1 - g0) / (n - 1)), bc,
+                                  dirichlet) for i in range(1, n + 1)]
+        else:
+            stages = [p]
         for k in range(1, nsteps + 1):
             dtk = dt if k < n_total else o.t_end - (k - 1) * dt
             L.or_step_begin(self.h, C.byref(p), float(dtk), _dp(We), _dp(be))
-            its, conv = self._newton_direct(p, We, be, dtk, o)
+            its = 0
+            for ps in stages:
+                i_s, conv = self._newton_direct(ps, We, be, dtk, o)
+                its += i_s
+                if conv < 0:
+                    break
             st["newton_total"] += its
             st["newton_max"] = max(st["newton_max"], its)
             st["capped"] += int(conv != 1)

@@ -37,7 +37,8 @@ class IC(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("gmres_m", C.c_int32), ("gmres_max_iters", C.c_int32),
                 ("newton_tol", C.c_double), ("gmres_rtol", C.c_double), ("cfl", C.c_double),
-                ("t_end", C.c_double), ("dt", C.c_double), ("max_steps", C.c_int32), ("timing", C.c_int32)]
+                ("t_end", C.c_double), ("dt", C.c_double), ("max_steps", C.c_int32), ("timing", C.c_int32),
+                ("forcing_max", C.c_double), ("cont_steps", C.c_int32), ("cont_gamma0", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -148,6 +149,9 @@ class Options:
     dt: float = 0.0
     max_steps: int = -1
     timing: int = 0
+    forcing_max: float = 0.0
+    cont_steps: int = 0
+    cont_gamma0: float = 0.0
 
     def c(self) -> SolveOpts:
         o = SolveOpts()

@@ -74,6 +74,9 @@ struct BInst {
   double newton_tol = 0, gmres_rtol = 0;
   double dt = 0, dtk = 0, t = 0, mass_cur = 0, active_cur = 0;
   int step = 0, nsteps = 0, n_total = 0;
+  int stage = 0, nstage = 1;   // continuation stage within the current step
+  int it_step = 0;             // Newton iterations of the current step (all stages)
+  double gamma_cur = 0;        // gamma of the current stage (0: the parameters' gamma)
   bool failed = false, cancelled = false;
   bsw_solve_stats st{};
   // Newton / backtracking
@@ -349,7 +352,9 @@ struct BatchEngine {
     BInst<T>* I = slots[k];
     InstDesc<T>& d = h_desc[k];
     d.m = view<T>(I->disc);
-    d.p = devparams<T>(I->prm, I->dtk > 0 ? I->dtk : I->dt);
+    bsw_params pc = I->prm;
+    if (I->gamma_cur > 0) pc.gamma = I->gamma_cur;
+    d.p = devparams<T>(pc, I->dtk > 0 ? I->dtk : I->dt);
     d.ws = I->ws;
     d.ld = I->ld;
     d.len = I->len;
@@ -519,8 +524,14 @@ struct BatchEngine {
     for (size_t a = 0; a < L.size(); ++a) rows[a] = tk.jv[a] + 1;
     if (int rc = final_rows(L, rows, 0, 0u, offA, 1, -1, jv)) return rc;
     // pass 2: w -= V h1; h2 = V^T w, w . w
-    hipLaunchKernelGGL((kb_axpy_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
-                       (int)B_V0, (int)B_WK);
+    int maxrows = 0;
+    for (int j : tk.jv) maxrows = std::max(maxrows, j + 1);
+    if (maxrows <= kRowsCached)
+      hipLaunchKernelGGL((kb_axpy_dots_cached<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc,
+                         offA, (int)B_V0, (int)B_WK);
+    else
+      hipLaunchKernelGGL((kb_axpy_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
+                         (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
     for (auto& r : rows) r += 1;
     if (int rc = final_rows(L, rows, 0, 0u, offB, 1, -1, jv)) return rc;
@@ -702,14 +713,75 @@ struct BatchEngine {
     for (int k = 0; k < kMaxBatch; ++k)
       if (slots[k] && !slots[k]->finished()) S.push_back(k);
     if (S.empty()) return BSW_OK;
+    // continuation stages (one unless requested), each a Newton solve from the
+    // last; gamma of stage i (0-based) of n: gamma0 + i (gamma - gamma0) / (n - 1)
+    auto stage_gamma = [](const BInst<T>* I, int stg) {
+      return I->nstage >= 2 ? I->opt.cont_gamma0 + stg * (I->prm.gamma - I->opt.cont_gamma0) / (I->nstage - 1) : 0.0;
+    };
     for (int k : S) {
       BInst<T>* I = slots[k];
       const int kk = I->step + 1;
       I->dtk = kk < I->n_total ? I->dt : I->opt.t_end - (kk - 1) * I->dt;
+      I->nstage = I->opt.cont_steps >= 2 ? I->opt.cont_steps : 1;
+      I->stage = 0;
+      I->it_step = 0;
+      I->conv = 0;
+      I->gamma_cur = stage_gamma(I, 0);
       fill_desc(k);
     }
     if (int rc = upload_desc()) return rc;
     if (int rc = step_begin(S)) return rc;
+    for (int stg = 0;; ++stg) {
+      std::vector<int> Sg;
+      for (int k : S) {
+        BInst<T>* I = slots[k];
+        if (stg >= I->nstage || I->conv < 0) continue;
+        Sg.push_back(k);
+      }
+      if (Sg.empty()) break;
+      if (stg > 0) {
+        // the previous stage ended with a stream synchronisation: the staging
+        // copy of the descriptors has completed and may be rewritten
+        for (int k : Sg) {
+          BInst<T>* I = slots[k];
+          I->stage = stg;
+          I->gamma_cur = stage_gamma(I, stg);
+          fill_desc(k);
+        }
+        if (int rc = upload_desc()) return rc;
+      }
+      if (int rc = newton(Sg)) return rc;
+    }
+    for (int k : S) {
+      slots[k]->gamma_cur = 0.0;
+      fill_desc(k);
+    }
+    if (int rc = upload_desc()) return rc;
+    if (int rc = diag(S)) return rc;
+    if (int rc = sync()) return rc;
+    for (int k : S) {
+      BInst<T>* I = slots[k];
+      I->st.newton_total += I->it_step;
+      I->st.newton_max = std::max(I->st.newton_max, I->it_step);
+      if (I->conv != 1) {
+        I->st.capped += 1;
+        I->st.status = BSW_W_NOT_CONVERGED;
+      }
+      I->mass_cur = rd(k, kScB);
+      I->active_cur = 100.0 * rd(k, kScB + 1) / I->disc->mesh->measure;
+      I->st.max_mass_drift = std::max(I->st.max_mass_drift, std::fabs(I->mass_cur - I->st.mass0) / I->st.mass0);
+      I->t += I->dtk;
+      I->step += 1;
+      I->st.steps = I->step;
+      if (I->conv < 0) I->failed = true;
+    }
+    return BSW_OK;
+  }
+
+  // Newton for the instances in S at the parameters in their descriptors:
+  // residual, then up to max_newton iterations of linearise, GMRES, update test
+  // and backtracking; it_step accumulates the iterations, conv the outcome
+  int newton(const std::vector<int>& S) {
     if (int rc = elem(0, S, B_W, B_W, B_R)) return rc;
     if (int rc = vred(S, B_R, -1, 0, kScB)) return rc;
     if (int rc = sync()) return rc;
@@ -720,7 +792,7 @@ struct BatchEngine {
       I->rn_prev = I->rn;
       I->it = 0;
       I->conv = 0;
-      I->eta = 1e-3;
+      I->eta = I->opt.forcing_max > 0 ? I->opt.forcing_max : 1e-2;
     }
     std::vector<int> N = S, C, L, A, nxt;
     std::vector<double> s;
@@ -728,13 +800,13 @@ struct BatchEngine {
       for (int k : N) {
         BInst<T>* I = slots[k];
         I->it += 1;
-        // Eisenstat-Walker forcing (choice 2, gamma 0.9, exponent 2) in [gmres_rtol, 1e-3]
+        // Eisenstat-Walker forcing (choice 2, gamma 0.9, exponent 2) in [gmres_rtol, forcing_max]
         if (I->it > 1) {
           const double r = I->rn / std::max(I->rn_prev, 1e-300);
           const double cand = 0.9 * r * r, safe = 0.9 * I->eta * I->eta;
           I->eta = std::max(cand, safe > 0.1 ? safe : 0.0);
         }
-        I->eta = std::min(1e-3, std::max(I->eta, I->gmres_rtol));
+        I->eta = std::min(I->opt.forcing_max > 0 ? I->opt.forcing_max : 1e-2, std::max(I->eta, I->gmres_rtol));
         I->rtol = I->eta;
       }
       if (int rc = linearize(N)) return rc;
@@ -797,24 +869,7 @@ struct BatchEngine {
         if (slots[k]->conv == 0 && slots[k]->it < slots[k]->opt.max_newton) nxt.push_back(k);
       N = nxt;
     }
-    if (int rc = diag(S)) return rc;
-    if (int rc = sync()) return rc;
-    for (int k : S) {
-      BInst<T>* I = slots[k];
-      I->st.newton_total += I->it;
-      I->st.newton_max = std::max(I->st.newton_max, I->it);
-      if (I->conv != 1) {
-        I->st.capped += 1;
-        I->st.status = BSW_W_NOT_CONVERGED;
-      }
-      I->mass_cur = rd(k, kScB);
-      I->active_cur = 100.0 * rd(k, kScB + 1) / I->disc->mesh->measure;
-      I->st.max_mass_drift = std::max(I->st.max_mass_drift, std::fabs(I->mass_cur - I->st.mass0) / I->st.mass0);
-      I->t += I->dtk;
-      I->step += 1;
-      I->st.steps = I->step;
-      if (I->conv < 0) I->failed = true;
-    }
+    for (int k : S) slots[k]->it_step += slots[k]->it;
     return BSW_OK;
   }
 
@@ -1086,6 +1141,7 @@ int check_request(bsw_ctx c, const bsw_solve_request* q) {
   if (o.max_newton < 1 || o.gmres_max_iters < 1 || !(o.t_end > 0) || o.gmres_m < 1 || o.gmres_m > 64)
     return fail(c, BSW_E_ARG, "bad solve options");
   if (!(o.dt > 0) && !(o.cfl > 0)) return fail(c, BSW_E_ARG, "need dt > 0 or cfl > 0");
+  if (o.cont_steps >= 2 && !(o.cont_gamma0 > 0)) return fail(c, BSW_E_ARG, "continuation needs cont_gamma0 > 0");
   const bsw_params* p = &q->params;
   if (p->reg < 1 || p->reg > 3 || p->bc < 1 || p->bc > 3) return fail(c, BSW_E_ARG, "bad reg or bc");
   if (!(p->g > 0) || !(p->rho > 0) || p->eta < 0 || p->sigma0 < 0 || !(p->gamma > 0) || !(p->beta > 0))
@@ -1320,6 +1376,8 @@ extern "C" int bsw_solve(bsw_disc d, const bsw_params* p, const bsw_solve_opts* 
   if (o->max_newton < 1 || o->gmres_max_iters < 1 || !(o->t_end > 0))
     return fail(d->mesh->ctx, BSW_E_ARG, "bad solve options");
   if (!(o->dt > 0) && !(o->cfl > 0)) return fail(d->mesh->ctx, BSW_E_ARG, "need dt > 0 or cfl > 0");
+  if (o->cont_steps >= 2 && !(o->cont_gamma0 > 0))
+    return fail(d->mesh->ctx, BSW_E_ARG, "continuation needs cont_gamma0 > 0");
   if (d->precision == BSW_FP64) return solve_one<double>(d, p, o, (double*)W, st);
   return solve_one<float>(d, p, o, (float*)W, st);
 }

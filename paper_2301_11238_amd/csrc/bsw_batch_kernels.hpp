@@ -280,6 +280,70 @@ __global__ void __launch_bounds__(256) kb_dots(const InstDesc<T>* __restrict__ d
 
 // w <- w - sum_{r <= j} h_r sigma_r V_r (h in row coff), then the partials of
 // V_r . w (r <= j) and w . w: the subtraction of pass 1 and the dots of pass 2
+// The same with each lane's entries of V_0..V_j kept in registers between the
+// subtraction and the dots (one read of the basis instead of two); for
+// instances with j + 1 <= kRowsCached.
+constexpr int kRowsCached = 32;
+
+template <class T>
+__global__ void __launch_bounds__(256) kb_axpy_dots_cached(const InstDesc<T>* __restrict__ ds, BatchSet A,
+                                                            const double* __restrict__ sc, int coff, int sV0,
+                                                            int sw) {
+  const int ai = bset_find(A, blockIdx.x);
+  const int slot = A.inst[ai];
+  const InstDesc<T> I = ds[slot];
+  const int t = blockIdx.x - A.tile0[ai];
+  const int rows = A.jv[ai] + 1;
+  const double* h = sc + (int64_t)slot * kScStride + coff;
+  const double* sg = sc + (int64_t)slot * kScStride + kScS;
+  const T* V = bslot(I, sV0, 0);
+  T* w = bslot(I, sw, 0);
+  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
+  const bool in0 = i0 < I.len, in1 = i1 < I.len;
+  T v0[kRowsCached], v1[kRowsCached];
+#pragma unroll
+  for (int r = 0; r < kRowsCached; ++r) {
+    const T* v = V + (int64_t)r * I.ld;
+    v0[r] = r < rows && in0 ? v[i0] : T(0);
+    v1[r] = r < rows && in1 ? v[i1] : T(0);
+  }
+  double a0 = in0 ? (double)w[i0] : 0.0, a1 = in1 ? (double)w[i1] : 0.0;
+#pragma unroll
+  for (int r = 0; r < kRowsCached; ++r) {
+    const double c = r < rows ? h[r] * sg[r] : 0.0;
+    a0 -= c * (double)v0[r];
+    a1 -= c * (double)v1[r];
+  }
+  if (in0) w[i0] = (T)a0;
+  if (in1) w[i1] = (T)a1;
+  const double w0 = in0 ? (double)(T)a0 : 0.0, w1 = in1 ? (double)(T)a1 : 0.0;
+  // partials of V_r . w (r < rows) and w . w (row `rows`), as tile_dots
+  __shared__ double red[8][257];
+  const int tid = threadIdx.x, ru = tid >> 5, rl = tid & 31;
+  const int nrow = rows + 1;
+#pragma unroll
+  for (int r0 = 0; r0 <= kRowsCached; r0 += 8) {
+    if (r0 < nrow) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = r0 + u;
+        double a = 0.0;
+        if (r < kRowsCached && r < rows) a = (double)v0[r < kRowsCached ? r : 0] * w0 + (double)v1[r < kRowsCached ? r : 0] * w1;
+        else if (r == rows) a = w0 * w0 + w1 * w1;
+        red[u][tid] = a;
+      }
+      __syncthreads();
+      double s2 = 0.0;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) s2 += red[ru][rl * 8 + m];
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+      if (rl == 0 && r0 + ru < nrow) I.part[(int64_t)(r0 + ru) * I.ntile + t] = s2;
+      __syncthreads();
+    }
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) kb_axpy_dots(const InstDesc<T>* __restrict__ ds, BatchSet A,
                                                      const double* __restrict__ sc, int coff, int sV0, int sw) {
