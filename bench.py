@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
                     help="c2: the 8192-triangle P2 incline (default); c3: the 131072-triangle P3 mesh of the "
                          "circular dam break (kernel timings only)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed leg of the solve")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving comparison (batched FP32 server vs plain FP64 solves)")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -107,6 +108,35 @@ def cpu_baseline(problem, seconds):
     return dict(value=n_dof * applies / el, unit="DOF-updates/s", cores=threads, kind="oracle",
                 sample=f"{applies} whole-mesh applies (operator + Jacobian, alternating) of the FP64 C oracle "
                        f"on the same 8192-triangle P2 mesh, {el:.1f} s")
+
+
+def fp32_leg(problem, mesh, cp, dt, args, W64, el64):
+    """The same warm-up and timed steps on the FP32-mixed path (FP32 state and
+    arithmetic, FP64 reductions and small-shear series), from the same
+    initial state; error of its final (h, h u) against the FP64 run's."""
+    import numpy as np
+    import torch
+    from paper_2301_11238_amd import bsw
+    d32 = bsw.Disc(mesh, problem.P, bsw.BSW_FP32)
+    W = d32.project_ic(problem.ic)
+    if args.warmup > 0:
+        d32.solve(cp, bsw.Options(t_end=(args.warmup + 0.5) * dt, dt=dt, max_steps=args.warmup, precond_lag=1), W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = d32.solve(cp, bsw.Options(t_end=(args.steps + 0.5) * dt, dt=dt, max_steps=args.steps, precond_lag=1), W)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    a = W.double().cpu().numpy()
+    b = W64.double().cpu().numpy()
+    h_a, h_b = a[0], b[0]
+    err_h = float(np.linalg.norm(h_a - h_b) / np.linalg.norm(h_b))
+    err_u = float(np.linalg.norm(a[1:3] - b[1:3]) / max(np.linalg.norm(b[1:3]), 1e-300))
+    d32.close()
+    return {"ms_per_step": 1e3 * el / args.steps, "speedup_vs_fp64": el64 / el,
+            "newton_per_step": st["newton_total"] / max(1, st["steps"]),
+            "gmres_per_step": st["gmres_total"] / max(1, st["steps"]),
+            "capped_steps": st["capped"],
+            "rel_l2_coeff_h_vs_fp64": err_h, "rel_l2_coeff_u_vs_fp64": err_u}
 
 
 def pct(xs, q):
@@ -230,19 +260,23 @@ def main():
         torch.cuda.synchronize()
         st = {"steps": 0, "newton_total": 0, "gmres_total": 0, "capped": 0}
         el, applies, value = 0.0, 0.0, 0.0
+        fp32 = None
     else:
         # warm-up steps, then exactly `steps` timed steps from where warm-up ended
         if args.warmup > 0:
-            disc.solve(cp, bsw.Options(t_end=(args.warmup + 0.5) * dt, dt=dt, max_steps=args.warmup), W)
+            disc.solve(cp, bsw.Options(t_end=(args.warmup + 0.5) * dt, dt=dt, max_steps=args.warmup, precond_lag=1), W)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = disc.solve(cp, bsw.Options(t_end=(args.steps + 0.5) * dt, dt=dt, max_steps=args.steps, timing=1), W)
+        st = disc.solve(cp, bsw.Options(t_end=(args.steps + 0.5) * dt, dt=dt, max_steps=args.steps, timing=1,
+                                        precond_lag=1), W)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         if st["steps"] != args.steps:
             raise RuntimeError(f"solve stopped after {st['steps']} of {args.steps} steps: {st}")
         applies = st["operator_applies"] + st["jacobian_applies"]
         value = n_dof * applies / el
+        if not args.no_fp32:
+            fp32 = fp32_leg(problem, mesh, cp, dt, args, W, el)
 
     # live roofline of the operator and Jacobian kernels (HIP events on the library's stream)
     b = disc.step_begin(cp, dt, W)
@@ -297,6 +331,8 @@ def main():
         "data": "synthetic (seeded jittered mesh, analytic initial mound)",
         "config": {"workload": "2-D Bingham flow on a 10% incline, 64x64 jittered -> 8192 triangles, "
                                "DG P2, reg 1, eps 1e-3, FP64, backward Euler at CFL 0.2",
+                   "solver": "Newton (<= 10 its, ||dW|| <= 1e-10 (1 + ||W||)), GMRES(30) with block-Jacobi "
+                             "kept across Newton iterations while it serves, forcing term <= 3e-2",
                    "n_el": n_el, "n_dof": n_dof, "dt": dt,
                    "newton_per_step": st["newton_total"] / max(1, st["steps"]),
                    "gmres_per_step": st["gmres_total"] / max(1, st["steps"]),
@@ -304,6 +340,7 @@ def main():
                    "applies_per_step": applies / max(1, st["steps"]),
                    "dof_steps_per_s": n_dof * st["steps"] / el},
         "roofline": roof,
+        "fp32_mixed": fp32 if not args.no_fp32 else None,
         "kernels": {name: {"ms": 1e3 * v["seconds"], "GB/s": v["bytes"] / v["seconds"] / 1e9}
                     for name, v in kern.items()},
     }

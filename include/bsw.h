@@ -102,12 +102,17 @@ typedef struct {
   int32_t max_steps;       /* < 0: all steps */
   int32_t timing;          /* nonzero: time every Jacobian-apply launch with HIP events */
   double forcing_max;      /* largest GMRES relative tolerance of a Newton system (the
-                              forcing term's ceiling); <= 0 selects 1e-2 */
+                              forcing term's ceiling); <= 0 selects 3e-2 */
   int32_t cont_steps;      /* continuation on gamma (Sec. 6.3): n >= 2 Newton solves per
                               time step at gamma_i = cont_gamma0 + (i-1)(gamma -
                               cont_gamma0)/(n-1), each starting from the last; beta and
                               the other parameters stay.  < 2: one solve at gamma */
   double cont_gamma0;      /* first gamma of the continuation (> 0 when cont_steps >= 2) */
+  int32_t precond_lag;     /* 0: rebuild the block-Jacobi preconditioner every Newton
+                              iteration; 1: build it at the first iteration of each
+                              Newton solve and keep it while GMRES converges within
+                              1.5x (+10) the iterations it took right after the build
+                              (the Jacobian products always use the current state) */
 } bsw_solve_opts;
 
 typedef struct {

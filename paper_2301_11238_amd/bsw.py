@@ -38,7 +38,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("gmres_m", C.c_int32), ("gmres_max_iters", C.c_int32),
                 ("newton_tol", C.c_double), ("gmres_rtol", C.c_double), ("cfl", C.c_double),
                 ("t_end", C.c_double), ("dt", C.c_double), ("max_steps", C.c_int32), ("timing", C.c_int32),
-                ("forcing_max", C.c_double), ("cont_steps", C.c_int32), ("cont_gamma0", C.c_double)]
+                ("forcing_max", C.c_double), ("cont_steps", C.c_int32), ("cont_gamma0", C.c_double),
+                ("precond_lag", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -152,6 +153,7 @@ class Options:
     forcing_max: float = 0.0
     cont_steps: int = 0
     cont_gamma0: float = 0.0
+    precond_lag: int = 0
 
     def c(self) -> SolveOpts:
         o = SolveOpts()

@@ -76,6 +76,8 @@ struct BInst {
   int step = 0, nsteps = 0, n_total = 0;
   int stage = 0, nstage = 1;   // continuation stage within the current step
   int it_step = 0;             // Newton iterations of the current step (all stages)
+  int gm_ref = 0, gm_last = 0; // GMRES iterations after the last preconditioner build, and last
+  bool gm_ok = true, rebuilt = false;
   double gamma_cur = 0;        // gamma of the current stage (0: the parameters' gamma)
   bool failed = false, cancelled = false;
   bsw_solve_stats st{};
@@ -239,10 +241,12 @@ struct BatchEngine {
     ++launches;
     return dispatchT<T>(dim, P, f);
   }
-  int linearize(const std::vector<int>& L) {
+  // traces of the linearisation state for all of L; diagonal blocks and their
+  // inverses for the instances in B (a subset of L)
+  int linearize(const std::vector<int>& L, const std::vector<int>& B) {
     if (int rc = trace(L, B_W, 0)) return rc;
     BatchSet S;
-    const int nt = build(S, L, K_E1);
+    const int nt = build(S, B, K_E1);
     if (!nt) return BSW_OK;
     auto f = [&]<int D, int PP, class TT>() -> int {
       using Sh = Shape<D, PP>;
@@ -792,7 +796,7 @@ struct BatchEngine {
       I->rn_prev = I->rn;
       I->it = 0;
       I->conv = 0;
-      I->eta = I->opt.forcing_max > 0 ? I->opt.forcing_max : 1e-2;
+      I->eta = I->opt.forcing_max > 0 ? I->opt.forcing_max : 3e-2;
     }
     std::vector<int> N = S, C, L, A, nxt;
     std::vector<double> s;
@@ -806,16 +810,31 @@ struct BatchEngine {
           const double cand = 0.9 * r * r, safe = 0.9 * I->eta * I->eta;
           I->eta = std::max(cand, safe > 0.1 ? safe : 0.0);
         }
-        I->eta = std::min(I->opt.forcing_max > 0 ? I->opt.forcing_max : 1e-2, std::max(I->eta, I->gmres_rtol));
+        I->eta = std::min(I->opt.forcing_max > 0 ? I->opt.forcing_max : 3e-2, std::max(I->eta, I->gmres_rtol));
         I->rtol = I->eta;
       }
-      if (int rc = linearize(N)) return rc;
+      // the block-Jacobi preconditioner is rebuilt every Newton iteration; with
+      // precond_lag it is built at the first iteration of a Newton solve and
+      // kept while it still serves: rebuilt when the last GMRES solve missed
+      // its tolerance or took more than 1.5x (+10) the iterations of the first
+      // solve after the last build
+      std::vector<int> Bk;
+      for (int k : N) {
+        BInst<T>* I = slots[k];
+        const bool stale = !I->gm_ok || I->gm_last > 1.5 * I->gm_ref + 10;
+        I->rebuilt = I->opt.precond_lag <= 0 || I->it == 1 || stale;
+        if (I->rebuilt) Bk.push_back(k);
+      }
+      if (int rc = linearize(N, Bk)) return rc;
       if (int rc = lin(N, B_RHS, B_R, B_R, -1.0, 0.0, 8)) return rc;
       if (int rc = gmres(N)) return rc;
       for (int k : N) {
         BInst<T>* I = slots[k];
         I->st.gmres_total += I->iters;
         I->st.jacobian_applies += I->iters + I->cycles;
+        I->gm_last = I->iters;
+        I->gm_ok = I->relres <= 10.0 * I->rtol;
+        if (I->rebuilt) I->gm_ref = I->iters;
       }
       // Newton test on the full update
       if (int rc = vred(N, B_DW, B_W, 1, kScB)) return rc;
