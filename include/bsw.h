@@ -70,6 +70,9 @@ typedef struct {
   int32_t reg;
   int32_t bc;
   double dirichlet[7];
+  int32_t jac_frozen;  /* Jacobian only: 0 exact (the HLL wave speeds S_L, S_R
+                          differentiated), 1 the paper's Appendix A form with
+                          S_L, S_R held fixed.  The residual is the same. */
 } bsw_params;
 
 /* Analytic initial condition, L2-projected with the element rule; E = 0.
@@ -178,9 +181,10 @@ int bsw_operator_apply(bsw_disc disc, const bsw_params* prm, double dt, const vo
  * diagonal blocks dR_e/dW_e of Eq. Newton and inverts them (LU with partial
  * pivoting) for the block-Jacobi preconditioner. */
 int bsw_jacobian_linearize(bsw_disc disc, const bsw_params* prm, double dt, const void* W);
-/* y = (dR/dW)(W) x, the exact directional derivative including the HLL wave
- * speeds and the face coupling to neighbours (matrix-free).  BSW_E_STATE
- * before the first linearize. */
+/* y = (dR/dW)(W) x, the directional derivative including the face coupling to
+ * neighbours (matrix-free): exact, HLL wave speeds included, or with them held
+ * fixed when prm->jac_frozen was set at linearize.  BSW_E_STATE before the
+ * first linearize. */
 int bsw_jacobian_apply(bsw_disc disc, const void* x, void* y);
 /* y = blockdiag(dR_e/dW_e)^{-1} x using the inverses of the last linearize. */
 int bsw_precond_apply(bsw_disc disc, const void* x, void* y);

@@ -39,7 +39,7 @@ class OrParams(C.Structure):
     _fields_ = [("g", C.c_double), ("rho", C.c_double), ("alpha", C.c_double),
                 ("eta", C.c_double), ("sigma0", C.c_double), ("gamma", C.c_double),
                 ("beta", C.c_double), ("reg", C.c_int32), ("bc", C.c_int32),
-                ("dir", C.c_double * MAXNF)]
+                ("dir", C.c_double * MAXNF), ("jac_frozen", C.c_int32)]
 
 
 class OrIC(C.Structure):
@@ -120,6 +120,7 @@ def make_params(params, bc: int = 1, dirichlet=None) -> OrParams:
         setattr(p, k, float(getattr(params, k)))
     p.reg = int(params.reg)
     p.bc = int(bc)
+    p.jac_frozen = int(getattr(params, "jac_frozen", 0))
     if dirichlet is not None:
         for i, v in enumerate(dirichlet):
             p.dir[i] = float(v)

@@ -45,6 +45,7 @@ typedef struct {
   int32_t reg;      /* 1, 2, 3 (Sec. 4, Eqs. sigmaTwoA, sigmaTwoB, sigmaTwoC) */
   int32_t bc;       /* 1 wall, 2 Neumann, 3 Dirichlet (Sec. 5.2) */
   double dir[MAXNF]; /* Dirichlet exterior values (h, u..., E...) */
+  int32_t jac_frozen; /* 1: the Jacobian holds S_L, S_R of the HLL flux fixed (Appendix A) */
 } or_params;
 
 typedef struct {
@@ -613,8 +614,9 @@ static void normal_flux_tan(const or_params* p, int dim, const pstate* s, const 
 }
 
 /* HLL flux (Eq. HLLSolver) with wave speeds u_n -+ sqrt(g h) evaluated on
- * both sides.  When dm/dp are given, also returns the exact directional
- * derivative dF (including the dependence of S_L, S_R). */
+ * both sides.  When dm/dp are given, also returns the directional derivative
+ * dF: exact (including the dependence of S_L, S_R), or with S_L, S_R held
+ * fixed as the paper's Appendix A does (p->jac_frozen). */
 static void or_hll(const or_params* p, int dim, const pstate* m, const pstate* pl,
                    const double* n, double* Fn, const pstate* dm, const pstate* dp, double* dFn) {
   int ne = 1 + dim;
@@ -644,6 +646,7 @@ static void or_hll(const or_params* p, int dim, const pstate* m, const pstate* p
   double dcm = 0.5 * p->g * dm->h / cm, dcp = 0.5 * p->g * dp->h / cp;
   double dSL = l1 <= l2 ? (dunm - dcm) : (dunp - dcp);
   double dSR = r1 >= r2 ? (dunm + dcm) : (dunp + dcp);
+  if (p->jac_frozen) dSL = dSR = 0.0;
   double den = SR - SL;
   for (int k = 0; k < ne; ++k) {
     double num = SR * Am[k] - SL * Ap[k] + SL * SR * (Up[k] - Um[k]);

@@ -25,7 +25,8 @@ class BswError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("rho", C.c_double), ("alpha", C.c_double), ("eta", C.c_double),
                 ("sigma0", C.c_double), ("gamma", C.c_double), ("beta", C.c_double),
-                ("reg", C.c_int32), ("bc", C.c_int32), ("dirichlet", C.c_double * 7)]
+                ("reg", C.c_int32), ("bc", C.c_int32), ("dirichlet", C.c_double * 7),
+                ("jac_frozen", C.c_int32)]
 
 
 class IC(C.Structure):
@@ -124,6 +125,7 @@ def make_params(p, bc: int = 1, dirichlet=None) -> Params:
         setattr(q, k, float(getattr(p, k)))
     q.reg = int(p.reg)
     q.bc = int(bc)
+    q.jac_frozen = int(getattr(p, "jac_frozen", 0))
     if dirichlet is not None:
         for i, v in enumerate(dirichlet):
             q.dirichlet[i] = float(v)

@@ -61,7 +61,7 @@ constexpr size_t kTabBytesTotal = tab_offset_rt(99, 99, true);
 template <class T>
 struct DevParams {
   T g, gc, gs, rho_inv, eta, s0, gam, bet, inv_dt;
-  int reg, bc;
+  int reg, bc, jfrozen;
   T dir[7];
 };
 
@@ -356,8 +356,9 @@ __device__ __forceinline__ void hll_tan(const DevParams<T>& p, const HLLState<D,
   }
   const T dcm = T(0.5) * p.g * dm.h / H.cm;
   const T dcp = T(0.5) * p.g * dp.h / H.cp;
-  const T dSL = H.left_m ? dunm - dcm : dunp - dcp;
-  const T dSR = H.right_m ? dunm + dcm : dunp + dcp;
+  // exact wave-speed derivatives, or none (the paper's frozen-speed form)
+  const T dSL = p.jfrozen ? T(0) : (H.left_m ? dunm - dcm : dunp - dcp);
+  const T dSR = p.jfrozen ? T(0) : (H.right_m ? dunm + dcm : dunp + dcp);
   const T inv = T(1) / (H.SR - H.SL);
   const T slsr = H.SL * H.SR;
   const T dslsr = dSL * H.SR + H.SL * dSR;

@@ -164,7 +164,7 @@ DevParams<T> devparams(const bsw_params& p, double dt) {
   q.rho_inv = (T)(1.0 / p.rho);
   q.eta = (T)p.eta; q.s0 = (T)p.sigma0; q.gam = (T)p.gamma; q.bet = (T)p.beta;
   q.inv_dt = dt > 0 ? (T)(1.0 / dt) : T(0);
-  q.reg = p.reg; q.bc = p.bc;
+  q.reg = p.reg; q.bc = p.bc; q.jfrozen = p.jac_frozen != 0;
   for (int k = 0; k < 7; ++k) q.dir[k] = (T)p.dirichlet[k];
   return q;
 }

@@ -213,3 +213,36 @@ def test_errors_are_reported(ctx):
     Wc = pr.dev(pr.orc.project_ic(wl.IC(kind=wl.IC_CONST, a=1.0)))
     st = pr.disc.solve(cp, bsw.Options(t_end=1e5, dt=1e-3, max_steps=2), Wc)
     assert st["steps"] == 2 and st["t_end"] == pytest.approx(2e-3)
+
+
+@pytest.mark.parametrize("dim,P,n", [(1, 2, 57), (2, 2, 9), (2, 3, 7)])
+def test_frozen_speed_jacobian_matches_oracle(ctx, dim, P, n):
+    """The paper-literal Jacobian (Appendix A: HLL wave speeds held fixed)."""
+    import dataclasses
+    from paper_2301_11238_amd import bsw
+    pr = make_pair(ctx, dim, P, n)
+    p = dataclasses.replace(prm_for(1), jac_frozen=1)
+    W = wl.random_state(dim, P, pr.disc.n_el, 310)
+    x = wl.random_vector(dim, P, pr.disc.n_el, 311)
+    dt = 0.017
+    pr.disc.jacobian_linearize(bsw.make_params(p), dt, pr.dev(W))
+    yg = pr.host(pr.disc.jacobian_apply(pr.dev(x)))
+    yo = pr.orc.jac_apply(p, W, x, dt)
+    assert relerr(yg, yo) <= 1e-11
+    ye = pr.orc.jac_apply(prm_for(1), W, x, dt)
+    assert relerr(ye, yo) > 1e-8  # the switch changes the product
+
+
+def test_frozen_speed_newton_solve_matches_oracle(ctx):
+    import dataclasses
+    import oracle
+    from paper_2301_11238_amd import bsw
+    pr = make_pair(ctx, 1, 1, 60)
+    p = wl.Params(eta=1.0, sigma0=50.0, gamma=100.0, beta=100.0, reg=1, jac_frozen=1)
+    W0 = pr.orc.project_ic(wl.IC(kind=wl.IC_STEP_X, a=1.0, b=0.1, x0=5.0))
+    Wo, so = pr.orc.solve(p, W0, oracle.SolveOptions(t_end=0.03, cfl=0.2, max_newton=60))
+    Wd = pr.dev(W0)
+    sg = pr.disc.solve(bsw.make_params(p), bsw.Options(t_end=0.03, cfl=0.2, max_newton=60), Wd)
+    assert so["capped"] == 0 and sg["capped"] == 0
+    eh, eq = rel_l2_h_hu(pr.orc, pr.host(Wd), Wo)
+    assert eh <= 1e-10 and eq <= 1e-10, (eh, eq)

@@ -152,6 +152,7 @@ class Params:
     gamma: float = 1e3          # regularisation parameter
     beta: float = 1e3           # smoothing parameter of regularisations 1, 2
     reg: int = REG1
+    jac_frozen: int = 0         # 1: Jacobian with the HLL wave speeds held fixed
 
     @staticmethod
     def from_eps(eps: float, **kw) -> "Params":
