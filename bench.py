@@ -331,8 +331,9 @@ def main():
         "data": "synthetic (seeded jittered mesh, analytic initial mound)",
         "config": {"workload": "2-D Bingham flow on a 10% incline, 64x64 jittered -> 8192 triangles, "
                                "DG P2, reg 1, eps 1e-3, FP64, backward Euler at CFL 0.2",
-                   "solver": "Newton (<= 10 its, ||dW|| <= 1e-10 (1 + ||W||)), GMRES(30) with block-Jacobi "
-                             "kept across Newton iterations while it serves, forcing term <= 3e-2",
+                   "solver": "Newton (<= 10 its, ||dW|| <= 1e-10 (1 + ||W||) or ||R|| <= 1e-13 ||b_old||), "
+                             "GMRES(30) with block-Jacobi kept across Newton iterations while it serves, "
+                             "forcing term <= 3e-2",
                    "n_el": n_el, "n_dof": n_dof, "dt": dt,
                    "newton_per_step": st["newton_total"] / max(1, st["steps"]),
                    "gmres_per_step": st["gmres_total"] / max(1, st["steps"]),

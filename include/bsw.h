@@ -116,6 +116,9 @@ typedef struct {
                               Newton solve and keep it while GMRES converges within
                               1.5x (+10) the iterations it took right after the build
                               (the Jacobian products always use the current state) */
+  double res_tol;          /* Newton also stops when ||R||_2 <= res_tol ||b_old||_2,
+                              checked on the initial and every accepted residual;
+                              0 selects 1e-13, a negative value turns it off */
 } bsw_solve_opts;
 
 typedef struct {

@@ -52,7 +52,7 @@ class OrSolveOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("gmres_m", C.c_int32),
                 ("gmres_max_restarts", C.c_int32), ("newton_tol", C.c_double),
                 ("gmres_rtol", C.c_double), ("cfl", C.c_double), ("t_end", C.c_double),
-                ("dt_override", C.c_double), ("max_steps", C.c_int32)]
+                ("dt_override", C.c_double), ("max_steps", C.c_int32), ("res_tol", C.c_double)]
 
 
 class OrSolveStats(C.Structure):
@@ -155,6 +155,9 @@ class SolveOptions:
     t_end: float = 1.0
     dt_override: float = 0.0
     max_steps: int = -1
+    # > 0: Newton also stops when ||R||_2 <= res_tol ||b_old||_2 (initial or
+    # accepted residual); the scope table's second stopping rule
+    res_tol: float = 1e-13
     # continuation on gamma (Sec. 6.3): n >= 2 Newton solves per time step at
     # gamma_i = gamma0 + (i - 1) (gamma - gamma0) / (n - 1), each from the last
     cont_steps: int = 0
@@ -263,12 +266,16 @@ class Oracle:
 
     def _newton_direct(self, p, We, be, dt, o):
         """Newton for one backward-Euler step with exact linear solves (sparse
-        LU); same iteration, line search and stopping rules as the C solver."""
+        LU); same iteration, line search and stopping rules as the C solver
+        (the update test, and the residual test when res_tol > 0)."""
         import scipy.sparse.linalg as spla
         L = lib()
         R = np.zeros_like(We)
         L.or_residual(self.h, C.byref(p), float(dt), _dp(We), _dp(be), _dp(R))
         rn = float(np.linalg.norm(R))
+        rstop = o.res_tol * float(np.linalg.norm(be)) if o.res_tol > 0 else -1.0
+        if np.isfinite(rn) and rn <= rstop:
+            return 0, 1
         conv, it = 0, 0
         for it in range(1, o.max_newton + 1):
             J = self._jacobian_sparse(p, We, dt)
@@ -291,6 +298,9 @@ class Oracle:
             R, rn = Rt, rnt
             if not np.isfinite(rnt) or not np.isfinite(We).all():
                 conv = -1
+                break
+            if rn <= rstop:
+                conv = 1
                 break
         return it, conv
 

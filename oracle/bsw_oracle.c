@@ -62,6 +62,7 @@ typedef struct {
   double cfl, t_end;
   double dt_override;   /* > 0: use this dt instead of the CFL rule */
   int32_t max_steps;    /* < 0: all */
+  double res_tol;       /* > 0: also stop when ||R||_2 <= res_tol ||b_old||_2 */
 } or_solve_opts;
 
 typedef struct {
@@ -1073,9 +1074,11 @@ static int gmres(lin_ctx* c, size_t n, const double* b, double* x, int m, double
 }
 
 /* One backward-Euler step by Newton (Eq. Newton, at most max_newton
- * iterations).  Each iteration solves J dW = -R with block-Jacobi GMRES and
- * stops (converged, the update applied) when ||dW||_inf <= newton_tol
- * (1 + ||W||_inf); otherwise takes the largest step a in {1, 1/2, ..., 1/64}
+ * iterations).  Converged when ||R||_2 <= res_tol ||b_old||_2 (res_tol > 0) for
+ * the initial or an accepted residual.  Each iteration solves J dW = -R with
+ * block-Jacobi GMRES and stops (converged, the update applied) when
+ * ||dW||_inf <= newton_tol (1 + ||W||_inf); otherwise takes the largest step a
+ * in {1, 1/2, ..., 1/64}
  * with ||R(W + a dW)|| <= (1 - 1e-4 a) ||R(W)|| (the smallest one if none does).
  * Returns the number of iterations; *conv = 1 converged, 0 capped, -1 non-finite. */
 int or_newton_step(void* h, const or_params* p, double dt, double* W, const double* bold,
@@ -1095,6 +1098,12 @@ int or_newton_step(void* h, const or_params* p, double dt, double* W, const doub
   *conv = 0; *gmres_its = 0;
   or_residual(D, p, dt, W, bold, R);
   double rn = sqrt(dot(n, R, R));
+  const double rstop = o->res_tol > 0 ? o->res_tol * sqrt(dot(n, bold, bold)) : -1.0;
+  if (isfinite(rn) && rn <= rstop) {
+    *conv = 1;
+    it = 0;
+    goto done;
+  }
   for (it = 1; it <= o->max_newton; ++it) {
     for (size_t k = 0; k < n; ++k) rhs[k] = -R[k];
     or_jac_blocks(D, p, dt, W, lu);
@@ -1132,8 +1141,10 @@ int or_newton_step(void* h, const or_params* p, double dt, double* W, const doub
     rn = rnt;
     (void)dmax; (void)wmax;
     if (bad) { *conv = -1; break; }
+    if (rn <= rstop) { *conv = 1; break; }
   }
   if (it > o->max_newton) it = o->max_newton;
+done:
   free(R); free(Rt); free(rhs); free(dW); free(Wt); free(lu); free(piv);
   return it;
 }

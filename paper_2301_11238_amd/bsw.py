@@ -40,7 +40,7 @@ class SolveOpts(C.Structure):
                 ("newton_tol", C.c_double), ("gmres_rtol", C.c_double), ("cfl", C.c_double),
                 ("t_end", C.c_double), ("dt", C.c_double), ("max_steps", C.c_int32), ("timing", C.c_int32),
                 ("forcing_max", C.c_double), ("cont_steps", C.c_int32), ("cont_gamma0", C.c_double),
-                ("precond_lag", C.c_int32)]
+                ("precond_lag", C.c_int32), ("res_tol", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -156,6 +156,7 @@ class Options:
     cont_steps: int = 0
     cont_gamma0: float = 0.0
     precond_lag: int = 0
+    res_tol: float = 0.0
 
     def c(self) -> SolveOpts:
         o = SolveOpts()

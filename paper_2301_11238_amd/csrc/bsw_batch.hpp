@@ -76,6 +76,7 @@ struct BInst {
   int step = 0, nsteps = 0, n_total = 0;
   int stage = 0, nstage = 1;   // continuation stage within the current step
   int it_step = 0;             // Newton iterations of the current step (all stages)
+  double bold_norm = 0;        // ||b_old||_2 of the current step (res_tol)
   int gm_ref = 0, gm_last = 0; // GMRES iterations after the last preconditioner build, and last
   bool gm_ok = true, rebuilt = false;
   double gamma_cur = 0;        // gamma of the current stage (0: the parameters' gamma)
@@ -323,13 +324,15 @@ struct BatchEngine {
     return BSW_OK;
   }
   // op 0: sum of squares, 1: max |x|, of slot s0 (and s1 >= 0) -> rows 0 (1)
-  // at off; sig >= 0 (op 0): the norm is written and sigma_{jv + sig} = 1 / norm
-  int vred(const std::vector<int>& L, int s0, int s1, int op, int off, int sig = -1) {
+  // at off; sig >= 0 (op 0): the norm is written and sigma_{jv + sig} = 1 / norm;
+  // vonly: over the first 1 + D fields only
+  int vred(const std::vector<int>& L, int s0, int s1, int op, int off, int sig = -1, int vonly = 0) {
     BatchSet S;
     const int nt = build(S, L, K_VEC);
     if (!nt) return BSW_OK;
     const int nr = s1 >= 0 ? 2 : 1;
-    hipLaunchKernelGGL((kb_vred<T>), dim3(nt, nr), dim3(256), 0, c->stream, d_desc, S, s0, s1 >= 0 ? s1 : s0, op);
+    hipLaunchKernelGGL((kb_vred<T>), dim3(nt, nr), dim3(256), 0, c->stream, d_desc, S, s0, s1 >= 0 ? s1 : s0, op,
+                       vonly);
     HIPCHK(c, hipGetLastError());
     ++launches;
     std::vector<int> rows(L.size(), nr);
@@ -362,6 +365,7 @@ struct BatchEngine {
     d.ws = I->ws;
     d.ld = I->ld;
     d.len = I->len;
+    d.len_v = I->len / (1 + dim + dim * dim) * (1 + dim);
     d.blk = (float*)I->disc->blocks;
     d.blk_raw = (T*)I->disc->blocks_raw;
     d.trL = (T*)I->disc->trL;
@@ -735,6 +739,15 @@ struct BatchEngine {
     }
     if (int rc = upload_desc()) return rc;
     if (int rc = step_begin(S)) return rc;
+    // ||b_old|| for the residual stopping test (res_tol)
+    std::vector<int> Sr;
+    for (int k : S)
+      if (res_tol_of(slots[k]) > 0) Sr.push_back(k);
+    if (!Sr.empty()) {
+      if (int rc = vred(Sr, B_BOLD, -1, 0, kScN + 4, -1, 1)) return rc;
+      if (int rc = sync()) return rc;
+      for (int k : Sr) slots[k]->bold_norm = std::sqrt(rd(k, kScN + 4));
+    }
     for (int stg = 0;; ++stg) {
       std::vector<int> Sg;
       for (int k : S) {
@@ -782,6 +795,14 @@ struct BatchEngine {
     return BSW_OK;
   }
 
+  // residual stopping test: ||R||_2 <= res_tol ||b_old||_2 (res_tol 0 selects
+  // 1e-13, a negative value turns it off)
+  static double res_tol_of(const BInst<T>* I) { return I->opt.res_tol == 0 ? 1e-13 : I->opt.res_tol; }
+  static bool res_converged(const BInst<T>* I) {
+    const double rt = res_tol_of(I);
+    return rt > 0 && std::isfinite(I->rn) && I->rn <= rt * I->bold_norm;
+  }
+
   // Newton for the instances in S at the parameters in their descriptors:
   // residual, then up to max_newton iterations of linearise, GMRES, update test
   // and backtracking; it_step accumulates the iterations, conv the outcome
@@ -795,10 +816,12 @@ struct BatchEngine {
       I->rn = std::sqrt(rd(k, kScB));
       I->rn_prev = I->rn;
       I->it = 0;
-      I->conv = 0;
+      I->conv = res_converged(I) ? 1 : 0;
       I->eta = I->opt.forcing_max > 0 ? I->opt.forcing_max : 3e-2;
     }
-    std::vector<int> N = S, C, L, A, nxt;
+    std::vector<int> N, C, L, A, nxt;
+    for (int k : S)
+      if (slots[k]->conv == 0) N.push_back(k);
     std::vector<double> s;
     while (!N.empty()) {
       for (int k : N) {
@@ -880,6 +903,7 @@ struct BatchEngine {
           I->rn_prev = I->rn;
           I->rn = I->rnt;
           if (!std::isfinite(I->rnt)) I->conv = -1;
+          else if (res_converged(I)) I->conv = 1;
         }
         L = nxt;
       }

@@ -55,6 +55,7 @@ struct InstDesc {
   T* ws;            // state vectors: slot k starts at ws + k * ld
   int64_t ld;
   int64_t len;      // n_f N_p n_el
+  int64_t len_v;    // (1 + D) N_p n_el: the entries of the first 1 + D fields
   float* blk;       // block-Jacobi inverses (FP32), [row][col][n_el]
   T* blk_raw;       // diagonal blocks, [n_el][row][col]
   T* trL;           // face traces of the linearisation state
@@ -453,20 +454,22 @@ __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restr
 
 // ------------------------------------------------------------------ per-instance reductions
 // partials of sum x^2 (op 0) or max |x| (op 1) over up to two slots
+// (vonly: only the first 1 + D fields, e.g. of b_old)
 template <class T>
 __global__ void __launch_bounds__(256) kb_vred(const InstDesc<T>* __restrict__ ds, BatchSet A, int s0, int s1,
-                                                int op) {
+                                                int op, int vonly) {
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int r = blockIdx.y;
   const int t = blockIdx.x - A.tile0[ai];
   const T* x = bslot(I, r == 0 ? s0 : s1, A.jv[ai]);
+  const int64_t lim = vonly ? I.len_v : I.len;
   double acc = 0.0;
   const int64_t i0 = (int64_t)t * kVT + threadIdx.x;
 #pragma unroll
   for (int k = 0; k < kVT / 256; ++k) {
     const int64_t i = i0 + k * 256;
-    if (i < I.len) {
+    if (i < lim) {
       const double v = (double)x[i];
       acc = op == 0 ? acc + v * v : fmax(acc, fabs(v));
     }
