@@ -13,10 +13,12 @@
 // its arithmetic is the same alone or in any mix.
 //
 // The server (bsw_server_s) owns one engine per (order, precision, restart
-// length), a FIFO of submitted requests and a worker thread.  Between steps
-// it admits queued requests while their device footprint fits the budget and
-// a slot is free, and retires finished ones (result copied to host memory,
-// device memory released): continuous batching at time-step granularity.
+// length), each with its own worker thread and HIP stream, and a FIFO of
+// submitted requests.  Between steps a worker admits its queued requests while
+// their device footprint fits the shared budget and a slot is free, and
+// retires finished ones (result copied to host memory, device memory
+// released): continuous batching at time-step granularity, batches of
+// different engines overlapping on the device.
 #pragma once
 
 #include <atomic>
@@ -117,7 +119,7 @@ struct BatchEngine {
   double* sch = nullptr;          // pinned, device-mapped mirror of sc
   double* sch_dev = nullptr;
   double* ystage = nullptr;       // pinned staging of Krylov combination weights
-  int64_t ticks = 0, launches = 0;
+  std::atomic<int64_t> ticks{0}, launches{0};
 
   ~BatchEngine() {
     destroy_events();
@@ -1027,46 +1029,64 @@ struct EngineImpl final : EngineIf {
 
 }  // namespace
 
+// One worker thread and one HIP stream per engine, so the batches of different
+// (order, precision, restart length) run concurrently on the device and a
+// slow batch does not hold up the others.
+struct EngineRec {
+  long key = 0;
+  bsw_ctx_s ctx;  // the engine's own context and stream
+  std::unique_ptr<EngineIf> eng;
+  std::thread th;
+};
+
 struct bsw_server_s {
   bsw_ctx user = nullptr;
-  bsw_ctx_s ictx;                 // the server's own context and stream
+  int device = 0;
   size_t budget = 0;
   int max_slots = 0;
   std::mutex mu;
   std::condition_variable cv, cv_done;
   std::deque<Request*> queue;
   std::map<uint64_t, std::unique_ptr<Request>> reqs;
-  std::map<long, std::unique_ptr<EngineIf>> engines;  // key: (P, precision, M)
+  std::map<long, std::unique_ptr<EngineRec>> engines;  // key: (P, precision, M)
   uint64_t next_ticket = 1;
   int64_t in_use = 0;
   int resident = 0, peak_resident = 0;
   int64_t steps = 0, completed = 0;
   bool stop = false;
-  std::thread th;
 
   static long key(const Request* r) { return ((long)r->P * 4 + r->precision) * 256 + r->M; }
 
-  EngineIf* engine_for(const Request* r, std::string& err) {
-    auto it = engines.find(key(r));
-    if (it != engines.end()) return it->second.get();
-    std::unique_ptr<EngineIf> E;
+  // under mu: the engine of r's key, created with its worker on first use
+  int ensure_engine(const Request* r, std::string& err) {
+    if (engines.count(key(r))) return BSW_OK;
+    auto rec = std::make_unique<EngineRec>();
+    rec->key = key(r);
+    rec->ctx.device = device;
+    if (hipStreamCreateWithFlags(&rec->ctx.stream, hipStreamNonBlocking) != hipSuccess) {
+      err = "hipStreamCreateWithFlags";
+      return BSW_E_HIP;
+    }
     int rc;
     if (r->precision == BSW_FP64) {
       auto* x = new EngineImpl<double>();
-      E.reset(x);
-      rc = x->e.init(&ictx, 2, r->P, r->M);
+      rec->eng.reset(x);
+      rc = x->e.init(&rec->ctx, 2, r->P, r->M);
     } else {
       auto* x = new EngineImpl<float>();
-      E.reset(x);
-      rc = x->e.init(&ictx, 2, r->P, r->M);
+      rec->eng.reset(x);
+      rc = x->e.init(&rec->ctx, 2, r->P, r->M);
     }
     if (rc) {
-      err = ictx.err;
-      return nullptr;
+      err = rec->ctx.err;
+      rec->eng.reset();
+      (void)hipStreamDestroy(rec->ctx.stream);
+      return rc;
     }
-    EngineIf* p = E.get();
-    engines[key(r)] = std::move(E);
-    return p;
+    EngineRec* p = rec.get();
+    engines[rec->key] = std::move(rec);
+    p->th = std::thread([this, p] { worker(p); });
+    return BSW_OK;
   }
 
   void finish(Request* r) {  // under mu
@@ -1078,58 +1098,48 @@ struct bsw_server_s {
     completed += 1;
   }
 
-  void run() {
-    (void)hipSetDevice(ictx.device);
+  // Between time steps: drop cancelled queued requests of this engine, admit
+  // its queued requests in FIFO order while the footprint fits the budget and
+  // a slot is free, step the batch, retire finished solves.
+  void worker(EngineRec* rec) {
+    (void)hipSetDevice(device);
+    EngineIf* E = rec->eng.get();
     std::vector<Request*> adm, out;
     for (;;) {
       adm.clear();
       {
         std::unique_lock<std::mutex> lk(mu);
         if (stop) break;
+        int free_slots = kMaxBatch - E->resident();
         for (auto it = queue.begin(); it != queue.end();) {
-          if ((*it)->cancel.load()) {
-            (*it)->state = BSW_REQ_CANCELLED;
-            it = queue.erase(it);
-            cv_done.notify_all();
-          } else {
+          Request* r = *it;
+          if (key(r) != rec->key) {
             ++it;
+            continue;
           }
-        }
-        // FIFO admission by footprint and slots
-        while (!queue.empty()) {
-          Request* r = queue.front();
-          if (resident >= max_slots || in_use + r->footprint > (int64_t)budget) break;
-          std::string err;
-          EngineIf* E = engine_for(r, err);
-          if (!E) {
-            queue.pop_front();
-            r->rc = BSW_E_HIP;
-            r->err = err;
-            r->state = BSW_REQ_FAILED;
+          if (r->cancel.load()) {
+            r->state = BSW_REQ_CANCELLED;
+            it = queue.erase(it);
             cv_done.notify_all();
             continue;
           }
-          if (!E->has_free()) break;
-          queue.pop_front();
+          if (resident >= max_slots || in_use + r->footprint > (int64_t)budget || free_slots <= 0) break;
+          it = queue.erase(it);
           resident += 1;
+          free_slots -= 1;
           in_use += r->footprint;
           peak_resident = std::max(peak_resident, resident);
           r->t_start = std::chrono::steady_clock::now();
           r->state = BSW_REQ_RUNNING;
           adm.push_back(r);
         }
-        if (adm.empty() && resident == 0) {
+        if (adm.empty() && E->resident() == 0) {
           cv.wait_for(lk, std::chrono::milliseconds(20));
           continue;
         }
       }
       for (Request* r : adm) {
         std::string err;
-        EngineIf* E;
-        {
-          std::lock_guard<std::mutex> lk(mu);
-          E = engines[key(r)].get();
-        }
         const int rc = E->admit(r, err);
         if (rc) {
           std::lock_guard<std::mutex> lk(mu);
@@ -1139,34 +1149,36 @@ struct bsw_server_s {
           completed -= 1;
           r->state = BSW_REQ_FAILED;
           cv_done.notify_all();
+          cv.notify_all();
         }
       }
-      for (auto& kv : engines) {
-        EngineIf* E = kv.second.get();
-        if (!E->resident()) continue;
-        out.clear();
-        const int rc = E->step();
-        if (rc < 0) {
-          const std::string err = ictx.err;
-          E->drop_all(out);
-          std::lock_guard<std::mutex> lk(mu);
-          for (Request* r : out) {
-            r->rc = rc;
-            r->err = err;
-            finish(r);
-            r->state = BSW_REQ_FAILED;
-          }
-          cv_done.notify_all();
-          continue;
-        }
-        E->retire(out);
+      if (!E->resident()) continue;
+      out.clear();
+      const int rc = E->step();
+      if (rc < 0) {
+        const std::string err = rec->ctx.err;
+        E->drop_all(out);
         std::lock_guard<std::mutex> lk(mu);
-        steps += 1;
         for (Request* r : out) {
+          r->rc = rc;
+          r->err = err;
           finish(r);
-          r->state = r->next_state;
+          r->state = BSW_REQ_FAILED;
         }
-        if (!out.empty()) cv_done.notify_all();
+        cv_done.notify_all();
+        cv.notify_all();
+        continue;
+      }
+      E->retire(out);
+      std::lock_guard<std::mutex> lk(mu);
+      steps += 1;
+      for (Request* r : out) {
+        finish(r);
+        r->state = r->next_state;
+      }
+      if (!out.empty()) {
+        cv_done.notify_all();
+        cv.notify_all();  // budget and slots freed: other engines may admit
       }
     }
   }
@@ -1208,14 +1220,9 @@ int bsw_server_create(bsw_ctx ctx, size_t hbm_budget_bytes, int max_slots, bsw_s
   HIPCHK(ctx, hipSetDevice(ctx->device));
   auto* S = new bsw_server_s();
   S->user = ctx;
-  S->ictx.device = ctx->device;
-  if (hipStreamCreateWithFlags(&S->ictx.stream, hipStreamNonBlocking) != hipSuccess) {
-    delete S;
-    return fail(ctx, BSW_E_HIP, "hipStreamCreateWithFlags");
-  }
+  S->device = ctx->device;
   S->budget = hbm_budget_bytes;
   S->max_slots = max_slots;
-  S->th = std::thread([S] { S->run(); });
   *out = S;
   return BSW_OK;
 }
@@ -1227,11 +1234,15 @@ int bsw_server_destroy(bsw_server S) {
     S->stop = true;
   }
   S->cv.notify_all();
-  if (S->th.joinable()) S->th.join();
-  (void)hipSetDevice(S->ictx.device);
-  (void)hipStreamSynchronize(S->ictx.stream);
+  for (auto& kv : S->engines)
+    if (kv.second->th.joinable()) kv.second->th.join();
+  (void)hipSetDevice(S->device);
+  for (auto& kv : S->engines) {
+    (void)hipStreamSynchronize(kv.second->ctx.stream);
+    kv.second->eng.reset();
+    (void)hipStreamDestroy(kv.second->ctx.stream);
+  }
   S->engines.clear();
-  (void)hipStreamDestroy(S->ictx.stream);
   delete S;
   return BSW_OK;
 }
@@ -1261,6 +1272,8 @@ int bsw_solve_submit(bsw_server S, const bsw_solve_request* q, uint64_t* ticket)
   r->t_submit = std::chrono::steady_clock::now();
   {
     std::lock_guard<std::mutex> lk(S->mu);
+    std::string err;
+    if (int rc = S->ensure_engine(r.get(), err)) return fail(S->user, rc, "batch engine: " + err);
     r->ticket = S->next_ticket++;
     *ticket = r->ticket;
     S->queue.push_back(r.get());
@@ -1329,7 +1342,7 @@ int bsw_server_info(bsw_server S, double* out8) {
   if (!S || !out8) return BSW_E_ARG;
   std::lock_guard<std::mutex> lk(S->mu);
   int64_t launches = 0;
-  for (auto& kv : S->engines) launches += kv.second->launches();
+  for (auto& kv : S->engines) launches += kv.second->eng->launches();
   out8[0] = (double)S->queue.size();
   out8[1] = (double)S->resident;
   out8[2] = (double)S->in_use;
