@@ -48,6 +48,11 @@ class OrIC(C.Structure):
                 ("L", C.c_double)]
 
 
+class OrBed(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("order", C.c_int32), ("a", C.c_double), ("kx", C.c_double),
+                ("ky", C.c_double), ("x0", C.c_double), ("y0", C.c_double), ("d", C.c_double)]
+
+
 class OrSolveOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("gmres_m", C.c_int32),
                 ("gmres_max_restarts", C.c_int32), ("newton_tol", C.c_double),
@@ -90,6 +95,8 @@ def lib():
                                      C.POINTER(OrSolveOpts), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.or_project_ic.argtypes = [C.c_void_p, C.POINTER(OrIC), dp]
         L.or_diagnostics.argtypes = [C.c_void_p, C.POINTER(OrParams), dp, dp]
+        L.or_bed_interpolate.argtypes = [C.c_void_p, C.POINTER(OrBed), dp]
+        L.or_set_bed.argtypes = [C.c_void_p, dp]
         L.or_eval_points.argtypes = [C.c_void_p, dp, dp]
         L.or_cfl_dt.restype = C.c_double
         L.or_cfl_dt.argtypes = [C.c_void_p, C.POINTER(OrParams), dp, C.c_double]
@@ -133,6 +140,26 @@ def make_ic(ic) -> OrIC:
     for k in ("a", "b", "c", "d", "x0", "y0", "r", "L"):
         setattr(c, k, float(getattr(ic, k)))
     return c
+
+
+def basis(dim: int, P: int, pts) -> tuple:
+    """Basis values [n_pts, N_p] and reference gradients [n_pts, N_p, 2] at
+    reference points (1-D: a vector of xi; 2-D: [n_pts, 2])."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    n = pts.shape[0]
+    np_ = P + 1 if dim == 1 else (P + 1) * (P + 2) // 2
+    phi = np.zeros((n, np_)); dphi = np.zeros((n, np_, 2))
+    lib().or_basis(dim, P, n, _dp(pts), _dp(phi), _dp(dphi))
+    return phi, dphi
+
+
+def make_bed(bed) -> OrBed:
+    b = OrBed()
+    b.kind = int(bed.kind)
+    b.order = int(bed.order)
+    for k in ("a", "kx", "ky", "x0", "y0", "d"):
+        setattr(b, k, float(getattr(bed, k)))
+    return b
 
 
 def to_elem(W: np.ndarray) -> np.ndarray:
@@ -209,6 +236,24 @@ class Oracle:
                            _dp(flen), _dp(xq), _dp(mh))
         return dict(nbr=nbr, nbr_face=nbrf, detJ=detJ, dxi=dxi, normal=normal, flen=flen,
                     xq=xq, measure=mh[0], hmin=mh[1])
+
+    # ------------------------------------------------------------------ bed
+    def bed_interpolate(self, bed) -> np.ndarray:
+        """Continuous order-m0 interpolant of an analytic bed (workloads.Bed),
+        as modal coefficients [N_p, n_el] (the layout of one state field)."""
+        H = np.zeros((self.n_el, self.np))
+        if lib().or_bed_interpolate(self.h, C.byref(make_bed(bed)), _dp(H)) != 0:
+            raise ValueError("bed order must be 1 <= m0 <= P")
+        return np.ascontiguousarray(H.T)
+
+    def set_bed(self, H) -> None:
+        """Bed coefficients [N_p, n_el] used by the source term; None = flat."""
+        if H is None:
+            lib().or_set_bed(self.h, None)
+            return
+        He = np.ascontiguousarray(np.asarray(H, dtype=np.float64).T)
+        assert He.shape == (self.n_el, self.np)
+        lib().or_set_bed(self.h, _dp(He))
 
     # ------------------------------------------------------------- operator
     def step_begin(self, params, Wold, dt, bc=1):

@@ -19,7 +19,9 @@
  *   - their exact tangent (Appendix A, chain rule), the element diagonal
  *     blocks, a block-Jacobi preconditioned restarted GMRES for Eq. Newton
  *     and the Newton / time loop (Sec. 5.1, Sec. 6: at most 10 iterations);
- *   - diagnostics: mass and the active-region percentage (Sec. 6).
+ *   - diagnostics: mass and the active-region percentage (Sec. 6);
+ *   - a variable bed H (Eq. Sterm, Sec. 5: H given at order m0 <= P) by
+ *     nodal interpolation that is continuous across faces.
  *
  * Layout inside the oracle: per-element blocks W[e][f][i] (f = field,
  * i = mode).  Field order: h, u_1..u_d, then E_ab = d u_b / d x_a stored at
@@ -52,6 +54,13 @@ typedef struct {
   int32_t kind;
   double a, b, c, d, x0, y0, r, L;
 } or_ic;
+
+/* Analytic bed: kind 0 flat, 1 a cos(kx x) cos(ky y) (1-D: a cos(kx x)),
+ * 2 a exp(-|x - (x0, y0)|^2 / d); order = m0 (0: P). */
+typedef struct {
+  int32_t kind, order;
+  double a, kx, ky, x0, y0, d;
+} or_bed;
 
 typedef struct {
   int32_t max_newton;   /* Sec. 6: at most 10 */
@@ -89,12 +98,14 @@ typedef struct {
   double *normal;        /* [n_el*nfc*2] */
   double *flen;          /* [n_el*nfc] */
   double *xq;            /* [n_el*nq*2] physical volume points */
+  double *vx;            /* [n_el*3*2] vertex coordinates */
   double total_measure, hmin;
 } or_mesh;
 
 typedef struct {
   or_ref ref;
   or_mesh mesh;
+  double *bed;           /* [n_el*np] modal coefficients of the bed H; NULL = flat */
 } or_disc;
 
 /* Legendre polynomial P_n and derivative by the three-term recursion. */
@@ -352,12 +363,14 @@ static int mesh_build(or_disc* D, int dim, int n_vert, const double* xy, int n_e
   M->normal = calloc((size_t)n_el * nfc * 2, sizeof(double));
   M->flen = malloc(sizeof(double) * n_el * nfc);
   M->xq = calloc((size_t)n_el * R->nq * 2, sizeof(double));
+  M->vx = calloc((size_t)n_el * 6, sizeof(double));
   M->total_measure = 0.0; M->hmin = 1e300;
   for (int e = 0; e < n_el; ++e) {
     const int32_t* v = e2v + (size_t)e * nvpe;
     if (dim == 1) {
       double x0 = xy[v[0]], x1 = xy[v[1]], L = x1 - x0;
       if (!(L > 0)) return -2;
+      M->vx[e * 6 + 0] = x0; M->vx[e * 6 + 2] = x1;
       M->detJ[e] = 0.5 * L;
       M->dxi[e * 4 + 0] = 2.0 / L;
       M->normal[(e * nfc + 0) * 2] = -1.0; M->normal[(e * nfc + 1) * 2] = 1.0;
@@ -368,6 +381,7 @@ static int mesh_build(or_disc* D, int dim, int n_vert, const double* xy, int n_e
     } else {
       double X[3], Y[3];
       for (int k = 0; k < 3; ++k) { X[k] = xy[2 * v[k]]; Y[k] = xy[2 * v[k] + 1]; }
+      for (int k = 0; k < 3; ++k) { M->vx[e * 6 + 2 * k] = X[k]; M->vx[e * 6 + 2 * k + 1] = Y[k]; }
       double a = X[1] - X[0], b = X[2] - X[0], c = Y[1] - Y[0], d = Y[2] - Y[0];
       double det = a * d - b * c;
       if (!(det > 0)) return -2;
@@ -542,9 +556,10 @@ static void unpack(int dim, const double* X, pstate* s) {
     for (int a = 0; a < dim; ++a) s->E[a][b] = X[1 + dim + b * dim + a];
 }
 
-/* U (Eq. Uterm), F_a (Eq. Fterm), Q_a (Eq. Qterm), S (Eq. Sterm, flat bed):
- * outputs over the 1+dim balance equations. */
-static void pointwise(const or_params* p, int dim, const pstate* s, double* U,
+/* U (Eq. Uterm), F_a (Eq. Fterm), Q_a (Eq. Qterm), S (Eq. Sterm):
+ * outputs over the 1+dim balance equations.  dH is the bed gradient at the
+ * point (NULL: flat bed). */
+static void pointwise(const or_params* p, int dim, const pstate* s, const double* dH, double* U,
                       double F[2][3], double Q[2][3], double* S) {
   double gc = p->g * cos(p->alpha), gs = p->g * sin(p->alpha);
   double sig[2][2];
@@ -560,12 +575,16 @@ static void pointwise(const or_params* p, int dim, const pstate* s, double* U,
     }
   }
   S[0] = 0.0;
-  for (int b = 0; b < dim; ++b) S[1 + b] = (b == 0) ? -gs * s->h : 0.0;
+  for (int b = 0; b < dim; ++b) {
+    S[1 + b] = (b == 0) ? -gs * s->h : 0.0;
+    if (dH) S[1 + b] -= gc * s->h * dH[b];
+  }
 }
 
 /* Tangents of the same maps (Appendix A: dU/dV, dF/dV, dQ/dV, dQ/dE, dS/dV). */
 static void pointwise_tan(const or_params* p, int dim, const pstate* s, const pstate* ds,
-                          double* dU, double dF[2][3], double dQ[2][3], double* dS) {
+                          const double* dH, double* dU, double dF[2][3], double dQ[2][3],
+                          double* dS) {
   double gc = p->g * cos(p->alpha), gs = p->g * sin(p->alpha);
   double sig[2][2], dsig[2][2][2][2];
   or_sigma(p, dim, (double(*)[2])s->E, sig, dsig);
@@ -584,7 +603,10 @@ static void pointwise_tan(const or_params* p, int dim, const pstate* s, const ps
     }
   }
   dS[0] = 0.0;
-  for (int b = 0; b < dim; ++b) dS[1 + b] = (b == 0) ? -gs * ds->h : 0.0;
+  for (int b = 0; b < dim; ++b) {
+    dS[1 + b] = (b == 0) ? -gs * ds->h : 0.0;
+    if (dH) dS[1 + b] -= gc * ds->h * dH[b];
+  }
 }
 
 /* Normal flux A(V; n) = sum_a F_a n_a and its tangent. */
@@ -725,12 +747,21 @@ static void element_eval(const or_disc* D, const or_params* p, double dt, const 
     pstate s, ds;
     unpack(dim, X, &s);
     double U[3], F[2][3], Q[2][3], S[3];
+    /* physical bed gradient dH/dx_a = sum_i H_i sum_r dphi_i/dxi_r dxi_r/dx_a */
+    double dH[2] = {0.0, 0.0};
+    if (D->bed) {
+      const double* He = D->bed + (size_t)e * np;
+      for (int a = 0; a < dim; ++a)
+        for (int i = 0; i < np; ++i)
+          for (int r = 0; r < dim; ++r) dH[a] += He[i] * R->dphi[q][i][r] * dxi[r * 2 + a];
+    }
+    const double* dHq = D->bed ? dH : NULL;
     if (tan) {
       eval_fields(R, R->phi[q], vown, dX);
       unpack(dim, dX, &ds);
-      pointwise_tan(p, dim, &s, &ds, U, F, Q, S);
+      pointwise_tan(p, dim, &s, &ds, dHq, U, F, Q, S);
     } else {
-      pointwise(p, dim, &s, U, F, Q, S);
+      pointwise(p, dim, &s, dHq, U, F, Q, S);
     }
     const double* Xv = tan ? dX : X;   /* E and u enter linearly in R_E */
     double wq = R->qw[q] * detJ;
@@ -777,8 +808,8 @@ static void element_eval(const or_disc* D, const or_params* p, double dt, const 
       if (!tan) {
         or_hll(p, dim, &sm, &sp, n, Fn, NULL, NULL, NULL);
         double U[3], F[2][3], Qm[2][3], Qp[2][3], S[3];
-        pointwise(p, dim, &sm, U, F, Qm, S);
-        pointwise(p, dim, &sp, U, F, Qp, S);
+        pointwise(p, dim, &sm, NULL, U, F, Qm, S);
+        pointwise(p, dim, &sp, NULL, U, F, Qp, S);
         for (int f = 0; f <= dim; ++f)
           for (int a = 0; a < dim; ++a) Qn[f] += 0.5 * (Qm[a][f] + Qp[a][f]) * n[a];
         for (int a = 0; a < dim; ++a)
@@ -787,8 +818,8 @@ static void element_eval(const or_disc* D, const or_params* p, double dt, const 
         double Fdummy[3];
         or_hll(p, dim, &sm, &sp, n, Fdummy, &dsm, &dsp, Fn);
         double dU[3], dF[2][3], dQm[2][3], dQp[2][3], dS[3];
-        pointwise_tan(p, dim, &sm, &dsm, dU, dF, dQm, dS);
-        pointwise_tan(p, dim, &sp, &dsp, dU, dF, dQp, dS);
+        pointwise_tan(p, dim, &sm, &dsm, NULL, dU, dF, dQm, dS);
+        pointwise_tan(p, dim, &sp, &dsp, NULL, dU, dF, dQp, dS);
         for (int f = 0; f <= dim; ++f)
           for (int a = 0; a < dim; ++a) Qn[f] += 0.5 * (dQm[a][f] + dQp[a][f]) * n[a];
         for (int a = 0; a < dim; ++a)
@@ -820,7 +851,7 @@ void or_destroy(void* h) {
   if (!D) return;
   or_mesh* M = &D->mesh;
   free(M->nbr); free(M->nbr_face); free(M->detJ); free(M->dxi); free(M->normal);
-  free(M->flen); free(M->xq); free(D);
+  free(M->flen); free(M->xq); free(M->vx); free(D->bed); free(D);
 }
 
 int or_sizes(void* h, int* out) {
@@ -1166,6 +1197,7 @@ static void ic_value(const or_ic* ic, int dim, const double* x, double* h, doubl
     case 7: *h = ic->a;
             u[0] = ic->b * sin(M_PI * X / ic->L) * cos(M_PI * Y / ic->L);
             u[1] = -ic->b * cos(M_PI * X / ic->L) * sin(M_PI * Y / ic->L); break;
+    case 8: *h = ic->a + ic->b * X; break;  /* free surface; the bed is subtracted below */
     default: *h = 1.0;
   }
 }
@@ -1209,8 +1241,117 @@ int or_project_ic(void* h, const or_ic* ic, double* W) {
         for (int b = 0; b < dim; ++b) We[(1 + b) * np + i] += R->qw[q] * R->phi[q][i] * u[b];
       }
     }
-    ic_positivity(R, We);
+    if (ic->kind == 8) {
+      /* h = a + b x - H: the linear surface is projected exactly, so h + H
+       * equals it in coefficient space and h is as continuous as H */
+      if (D->bed)
+        for (int i = 0; i < np; ++i) We[i] -= D->bed[(size_t)e * np + i];
+    } else {
+      ic_positivity(R, We);
+    }
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ bed */
+static double bed_value(const or_bed* b, int dim, double X, double Y) {
+  switch (b->kind) {
+    case 1: return b->a * cos(b->kx * X) * (dim == 2 ? cos(b->ky * Y) : 1.0);
+    case 2: { double r2 = (X - b->x0) * (X - b->x0) + (dim == 2 ? (Y - b->y0) * (Y - b->y0) : 0.0);
+              return b->a * exp(-r2 / b->d); }
+    default: return 0.0;
+  }
+}
+
+/* Interior Gauss-Lobatto points of order m on [-1, 1] (the roots of P_m'),
+ * closed forms for m <= 4. */
+static int lobatto_interior(int m, double* t) {
+  switch (m) {
+    case 1: return 0;
+    case 2: t[0] = 0.0; return 1;
+    case 3: t[0] = -1.0 / sqrt(5.0); t[1] = 1.0 / sqrt(5.0); return 2;
+    case 4: t[0] = -sqrt(3.0 / 7.0); t[1] = 0.0; t[2] = sqrt(3.0 / 7.0); return 3;
+  }
+  return -1;
+}
+
+/* Interpolation nodes of order m on the reference element, chosen so that
+ * the nodes on a face are the same physical points seen from both elements:
+ * in 1-D the Gauss-Lobatto points; on the triangle the three vertices, the
+ * interior Gauss-Lobatto points of every edge (symmetric about its midpoint)
+ * and, for m = 3, the centroid.  Returns the node count. */
+static int bed_nodes(int dim, int m, double (*xi)[2]) {
+  double t[4];
+  int ni = lobatto_interior(m, t), k = 0;
+  if (ni < 0) return -1;
+  if (dim == 1) {
+    xi[k][0] = -1.0; xi[k++][1] = 0.0;
+    for (int j = 0; j < ni; ++j) { xi[k][0] = t[j]; xi[k++][1] = 0.0; }
+    xi[k][0] = 1.0; xi[k++][1] = 0.0;
+    return k;
+  }
+  if (m > 3) return -1;
+  const double V[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+  for (int v = 0; v < 3; ++v) { xi[k][0] = V[v][0]; xi[k++][1] = V[v][1]; }
+  for (int f = 0; f < 3; ++f)
+    for (int j = 0; j < ni; ++j) {
+      double s = 0.5 * (t[j] + 1.0);
+      const double* A = V[f]; const double* B = V[(f + 1) % 3];
+      xi[k][0] = A[0] + s * (B[0] - A[0]); xi[k++][1] = A[1] + s * (B[1] - A[1]);
+    }
+  if (m == 3) { xi[k][0] = 1.0 / 3.0; xi[k++][1] = 1.0 / 3.0; }
+  return k;
+}
+
+/* Bed of order m0 <= P (Sec. 5: H is given and projected at order m0; the
+ * depth and the bed discretised alike): the interpolant of H at the order-m0
+ * nodes, whose face traces agree between neighbours.  Both bases are
+ * hierarchical by total degree, so the interpolant is spanned by the first
+ * N(m0) modes; the Vandermonde system of those modes at the nodes gives its
+ * coefficients and the higher modes are zero.  Out: H[e*np + i]. */
+int or_bed_interpolate(void* h, const or_bed* bed, double* H) {
+  or_disc* D = h; or_ref* R = &D->ref; or_mesh* M = &D->mesh;
+  int dim = R->dim, np = R->np, m = bed->order > 0 ? bed->order : R->P;
+  if (m > R->P || m < 1) return -1;
+  double xi[MAXNP][2];
+  int nn = bed_nodes(dim, m, xi);
+  if (nn < 0) return -1;
+  int nm = dim == 1 ? m + 1 : (m + 1) * (m + 2) / 2;
+  if (nn != nm) return -1;
+  double Vd[MAXNP * MAXNP]; int piv[MAXNP];
+  for (int j = 0; j < nn; ++j) {
+    double ph[MAXNP];
+    if (dim == 1) legendre_basis(R->P, xi[j][0], ph, NULL);
+    else dubiner(R->P, xi[j][0], xi[j][1], ph, NULL);
+    for (int k = 0; k < nm; ++k) Vd[j * nm + k] = ph[k];
+  }
+  if (lu_factor(nm, Vd, piv)) return -1;
+  for (int e = 0; e < M->n_el; ++e) {
+    const double* v = M->vx + (size_t)e * 6;
+    double c[MAXNP];
+    for (int j = 0; j < nn; ++j) {
+      double X, Y = 0.0;
+      if (dim == 1) X = v[0] + 0.5 * (xi[j][0] + 1.0) * (v[2] - v[0]);
+      else {
+        X = v[0] + xi[j][0] * (v[2] - v[0]) + xi[j][1] * (v[4] - v[0]);
+        Y = v[1] + xi[j][0] * (v[3] - v[1]) + xi[j][1] * (v[5] - v[1]);
+      }
+      c[j] = bed_value(bed, dim, X, Y);
+    }
+    lu_solve(nm, Vd, piv, c);
+    for (int i = 0; i < np; ++i) H[(size_t)e * np + i] = i < nm ? c[i] : 0.0;
+  }
+  return 0;
+}
+
+/* Sets the bed used by the source term (a copy; NULL = flat). */
+int or_set_bed(void* h, const double* H) {
+  or_disc* D = h;
+  free(D->bed); D->bed = NULL;
+  if (!H) return 0;
+  size_t n = (size_t)D->mesh.n_el * D->ref.np;
+  D->bed = malloc(sizeof(double) * n);
+  memcpy(D->bed, H, sizeof(double) * n);
   return 0;
 }
 

@@ -39,6 +39,11 @@ IC_SINE_U = 4     # h = a ; u1 = b*sin(pi*x/L)                (decaying shear fl
 IC_LINEAR_X = 5   # h = a + b*x ; u = 0                      (tilted lake at rest)
 IC_SHEAR_Y = 6    # h = a ; u1 = b*cos(pi*y/L)                (decaying shear mode)
 IC_VORTEX = 7     # h = a ; u = b*(sin(pi x/L)cos(pi y/L), -cos(pi x/L)sin(pi y/L))
+IC_SURFACE = 8    # h = a + b*x - H(x) ; u = 0 (free surface over the bed H)
+
+BED_FLAT = 0      # H = 0
+BED_COS = 1       # H = a cos(kx x) cos(ky y)   (1-D: a cos(kx x))
+BED_GAUSS = 2     # H = a exp(-|x - (x0, y0)|^2 / d)
 
 REG1, REG2, REG3 = 1, 2, 3
 
@@ -172,6 +177,19 @@ class IC:
     y0: float = 0.0
     r: float = 0.0
     L: float = 1.0
+
+
+@dataclass
+class Bed:
+    """Analytic bed H; order = m0, the interpolation order (0: the disc's P)."""
+    kind: int = BED_FLAT
+    order: int = 0
+    a: float = 0.0
+    kx: float = 0.0
+    ky: float = 0.0
+    x0: float = 0.0
+    y0: float = 0.0
+    d: float = 1.0
 
 
 @dataclass
