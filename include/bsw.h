@@ -52,8 +52,10 @@ enum { BSW_REG1 = 1, BSW_REG2 = 2, BSW_REG3 = 3 };
 enum { BSW_BC_WALL = 1, BSW_BC_NEUMANN = 2, BSW_BC_DIRICHLET = 3 };
 enum {
   BSW_IC_CONST = 0, BSW_IC_STEP_X = 1, BSW_IC_MOUND = 2, BSW_IC_DISK = 3,
-  BSW_IC_SINE_U = 4, BSW_IC_LINEAR_X = 5, BSW_IC_SHEAR_Y = 6, BSW_IC_VORTEX = 7
+  BSW_IC_SINE_U = 4, BSW_IC_LINEAR_X = 5, BSW_IC_SHEAR_Y = 6, BSW_IC_VORTEX = 7,
+  BSW_IC_SURFACE = 8
 };
+enum { BSW_BED_FLAT = 0, BSW_BED_COS = 1, BSW_BED_GAUSS = 2 };
 
 typedef struct bsw_ctx_s* bsw_ctx;
 typedef struct bsw_mesh_s* bsw_mesh;
@@ -81,11 +83,25 @@ typedef struct {
  * depth modes are scaled so that the minimum is a tenth of the mean.
  * kinds: CONST h=a,u=(b,c); STEP_X h = x<x0 ? a : b; MOUND h = a+b exp(-|x-x0,y0|^2/d);
  * DISK h = |x-(x0,y0)|<r ? a : b; SINE_U h=a,u1=b sin(pi x/L); LINEAR_X h=a+b x;
- * SHEAR_Y h=a,u1=b cos(pi y/L); VORTEX h=a, u=b(sin(pi x/L)cos(pi y/L), -cos(pi x/L)sin(pi y/L)). */
+ * SHEAR_Y h=a,u1=b cos(pi y/L); VORTEX h=a, u=b(sin(pi x/L)cos(pi y/L), -cos(pi x/L)sin(pi y/L));
+ * SURFACE h = a + b x1 - H with H the discretisation's bed (bsw_disc_set_bed;
+ * zero when flat), u = 0: the linear free surface is projected exactly and the
+ * bed coefficients subtracted, so h + H equals it mode by mode and h is as
+ * continuous across faces as H (Sec. 6.1 and 6.2 initial states); no
+ * positivity scaling. */
 typedef struct {
   int32_t kind;
   double a, b, c, d, x0, y0, r, L;
 } bsw_ic;
+
+/* Analytic bed height H of the momentum source -g_c h dH/dx (Eq. Sterm):
+ * FLAT H = 0; COS H = a cos(kx x1) cos(ky x2) (1-D: a cos(kx x1));
+ * GAUSS H = a exp(-|x - (x0, y0)|^2 / d).  order = m0, the polynomial order of
+ * the bed (Sec. 5: H is projected at order m0; 1 <= m0 <= P, 0 selects P). */
+typedef struct {
+  int32_t kind, order;
+  double a, kx, ky, x0, y0, d;
+} bsw_bed;
 
 /* Whole-solve controls (Sec. 5.1 and Sec. 6: at most max_newton = 10 Newton
  * iterations per step).  dt > 0 fixes the step; otherwise
@@ -164,6 +180,23 @@ int64_t bsw_state_len(bsw_disc disc);
 /* L2 projection of an analytic initial condition into W (device). */
 int bsw_project_ic(bsw_disc disc, const bsw_ic* ic, void* W);
 
+/* ---------------------------------------------------------------- variable bed (Eq. Sterm, Sec. 5, Sec. 6.1) */
+/* Writes the order-m0 interpolant of bed into H (device, n_p * n_el reals of
+ * the discretisation's precision, layout [i][e] like one field of W).  The
+ * nodes are shared by neighbouring elements: Gauss-Lobatto points in 1-D; on
+ * triangles the vertices, the interior Gauss-Lobatto points of each edge and,
+ * for m0 = 3, the centroid.  The interpolant's face traces therefore agree,
+ * which the lake at rest needs (the HLL flux damps depth jumps).  Modes of
+ * degree above m0 are zero.  BSW_E_ARG for m0 outside 1..P (1-D: P <= 4,
+ * triangles: P <= 3) or a bad kind. */
+int bsw_bed_interpolate(bsw_disc disc, const bsw_bed* bed, void* H);
+/* Sets the bed of the momentum source: H (device, layout as above) is kept by
+ * reference and must stay valid and unchanged while the discretisation uses
+ * it; NULL returns to the flat bed.  The next operator, linearize and solve
+ * calls use it; a Jacobian linearized before the call must be linearized
+ * again (BSW_E_STATE until then). */
+int bsw_disc_set_bed(bsw_disc disc, const void* H);
+
 /* ---------------------------------------------------------------- the operator */
 /* b_old[f][i][e] = (1/dt) <phi_i, U_f(W_old)>_e for f < 1+d: the old-time part
  * of the first term of Eq. WeakForm7 (U = (h, h u), Eq. Uterm). */
@@ -172,7 +205,8 @@ int bsw_step_begin(bsw_disc disc, const bsw_params* prm, double dt, const void* 
 
 /* R = the element residuals of Eq. WeakForm7 at W given b_old: volume fluxes
  * F (Eq. Fterm), the regularised Bingham stress term Q (Eq. Qterm, Sec. 4),
- * the source S (Eq. Sterm, flat bed), the auxiliary equation for E (Eq. Gterm),
+ * the source S (Eq. Sterm, with the bed set by bsw_disc_set_bed), the auxiliary
+ * equation for E (Eq. Gterm),
  * HLL face fluxes for F (Eq. HLLSolver) and central ones for Q and G (Sec. 5).
  * Layout of R as W.  W, b_old and R must not alias. */
 int bsw_operator_apply(bsw_disc disc, const bsw_params* prm, double dt, const void* W,
@@ -245,7 +279,9 @@ enum { BSW_REQ_QUEUED = 0, BSW_REQ_RUNNING = 1, BSW_REQ_DONE = 2, BSW_REQ_FAILED
  * bsw_solve_submit, so the caller may free them on return.  Mesh as for
  * bsw_mesh_upload (dim = 2): xy[2 n_vert], el2vert[3 n_el].  W0 (optional)
  * is an initial state of n_f n_p n_el reals of the request's precision in the
- * SoA layout; when NULL the initial condition ic is projected. */
+ * SoA layout; when NULL the initial condition ic is projected.  bed (kind
+ * BSW_BED_FLAT when zero-initialised) is interpolated as by bsw_bed_interpolate
+ * into memory of the request and set before ic is projected. */
 typedef struct {
   int64_t n_vert;
   const double* xy;
@@ -257,11 +293,13 @@ typedef struct {
   bsw_ic ic;
   const void* W0;
   bsw_solve_opts opts;
+  bsw_bed bed;
 } bsw_solve_request;
 
 /* Device bytes a request occupies while resident: state and 11 + gmres_m
  * work vectors, the diagonal Jacobian blocks and their inverses, reduction
- * partials and mesh arrays.  -1 for an invalid request. */
+ * partials, mesh arrays and the bed coefficients (counted for every request).
+ * -1 for an invalid request. */
 int64_t bsw_request_footprint(const bsw_solve_request* req);
 int bsw_server_create(bsw_ctx ctx, size_t hbm_budget_bytes, int max_slots, bsw_server* out);
 /* Stops the worker after its current step; unfinished requests are dropped. */

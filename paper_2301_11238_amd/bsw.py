@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libbsw.so")
 
 BSW_OK, BSW_W_NOT_CONVERGED = 0, 1
 BSW_FP64, BSW_FP32 = 0, 1
+BSW_IC_SURFACE = 8
+BSW_BED_FLAT, BSW_BED_COS, BSW_BED_GAUSS = 0, 1, 2
 
 
 class BswError(RuntimeError):
@@ -33,6 +35,11 @@ class IC(C.Structure):
     _fields_ = [("kind", C.c_int32), ("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
                 ("d", C.c_double), ("x0", C.c_double), ("y0", C.c_double), ("r", C.c_double),
                 ("L", C.c_double)]
+
+
+class Bed(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("order", C.c_int32), ("a", C.c_double), ("kx", C.c_double),
+                ("ky", C.c_double), ("x0", C.c_double), ("y0", C.c_double), ("d", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -56,7 +63,7 @@ class SolveStats(C.Structure):
 class SolveRequest(C.Structure):
     _fields_ = [("n_vert", C.c_int64), ("xy", C.POINTER(C.c_double)), ("n_el", C.c_int64),
                 ("el2vert", C.POINTER(C.c_int32)), ("P", C.c_int32), ("precision", C.c_int32),
-                ("params", Params), ("ic", IC), ("W0", C.c_void_p), ("opts", SolveOpts)]
+                ("params", Params), ("ic", IC), ("W0", C.c_void_p), ("opts", SolveOpts), ("bed", Bed)]
 
 
 BSW_REQ_QUEUED, BSW_REQ_RUNNING, BSW_REQ_DONE, BSW_REQ_FAILED, BSW_REQ_CANCELLED = range(5)
@@ -75,6 +82,8 @@ SIGNATURES = {
     "bsw_disc_info": (C.c_int, [_VP, _I64P]),
     "bsw_state_len": (C.c_int64, [_VP]),
     "bsw_project_ic": (C.c_int, [_VP, C.POINTER(IC), _VP]),
+    "bsw_bed_interpolate": (C.c_int, [_VP, C.POINTER(Bed), _VP]),
+    "bsw_disc_set_bed": (C.c_int, [_VP, _VP]),
     "bsw_step_begin": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP, _VP]),
     "bsw_operator_apply": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP, _VP, _VP]),
     "bsw_jacobian_linearize": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP]),
@@ -138,6 +147,18 @@ def make_ic(ic) -> IC:
     for k in ("a", "b", "c", "d", "x0", "y0", "r", "L"):
         setattr(c, k, float(getattr(ic, k)))
     return c
+
+
+def make_bed(bed) -> Bed:
+    """bed: workloads.Bed (or anything with the same attributes)."""
+    b = Bed()
+    if bed is None:
+        return b
+    b.kind = int(bed.kind)
+    b.order = int(bed.order)
+    for k in ("a", "kx", "ky", "x0", "y0", "d"):
+        setattr(b, k, float(getattr(bed, k)))
+    return b
 
 
 @dataclass
@@ -269,6 +290,17 @@ class Disc:
         self._ck(lib().bsw_project_ic(self.h, C.byref(make_ic(ic)), _ptr(W)))
         return W
 
+    def bed_interpolate(self, bed, H=None):
+        """Order-m0 interpolant of an analytic bed, [N_p, n_el] on the device."""
+        H = self.empty(1) if H is None else H
+        self._ck(lib().bsw_bed_interpolate(self.h, C.byref(make_bed(bed)), _ptr(H)))
+        return H[0] if H.dim() == 3 else H
+
+    def set_bed(self, H):
+        """Bed coefficients [N_p, n_el] (device tensor kept by reference), or None."""
+        self._bed = H
+        self._ck(lib().bsw_disc_set_bed(self.h, _ptr(H) if H is not None else None))
+
     def step_begin(self, params: Params, dt: float, W_old, b_old=None):
         b_old = self.empty(1 + self.dim) if b_old is None else b_old
         self._ck(lib().bsw_step_begin(self.h, C.byref(params), float(dt), _ptr(W_old), _ptr(b_old)))
@@ -331,7 +363,7 @@ class Disc:
 class _ReqArrays:
     """Keeps the host arrays of a request alive until it is submitted."""
 
-    def __init__(self, xy, el2vert, P, precision, params, ic, opts, W0=None):
+    def __init__(self, xy, el2vert, P, precision, params, ic, opts, W0=None, bed=None):
         import numpy as np
         self.xy = np.ascontiguousarray(xy, dtype=np.float64)
         self.e2v = np.ascontiguousarray(el2vert, dtype=np.int32)
@@ -349,6 +381,7 @@ class _ReqArrays:
         r.ic = make_ic(ic) if ic is not None else IC()
         r.W0 = C.c_void_p(self.W0.ctypes.data) if self.W0 is not None else None
         r.opts = opts.c()
+        r.bed = make_bed(bed)
         self.req = r
 
 
@@ -383,9 +416,9 @@ class Server:
             pass
 
     def submit(self, xy, el2vert, P: int, precision: int, params: Params, ic=None, opts: Options = None,
-               W0=None) -> int:
+               W0=None, bed=None) -> int:
         opts = opts or Options()
-        a = _ReqArrays(xy, el2vert, P, precision, params, ic, opts, W0)
+        a = _ReqArrays(xy, el2vert, P, precision, params, ic, opts, W0, bed)
         t = C.c_uint64(0)
         self.ctx._check(lib().bsw_solve_submit(self.h, C.byref(a.req), C.byref(t)), self.ctx.h)
         n_p = (P + 1) * (P + 2) // 2

@@ -56,6 +56,7 @@ int64_t instance_bytes(int64_t n_el, int dim, int P, int precision, int M) {
   b += std::max<int64_t>(std::max<int64_t>(66 * ntile, 4 * ntile_e), 4096) * 8;
   const int64_t geo = dim * dim + 1 + (dim + 1) * (dim + 1);
   b += n_el * ((dim + 1) * 4 + (dim + 1) * dim * 8 + geo * 8 + (precision == BSW_FP32 ? geo * 4 : 0));
+  b += n_modes(dim, P) * n_el * w;  // bed coefficients
   return b + 4096;
 }
 
@@ -68,6 +69,7 @@ struct BInst {
   bsw_mesh mesh = nullptr;
   bsw_disc disc = nullptr;
   T* ws = nullptr;
+  T* bed = nullptr;  // bed coefficients of a served solve with a variable bed
   int64_t n_el = 0, len = 0, ld = 0;
   int ntile = 0, ntile_e = 0;
   double* part = nullptr;
@@ -102,6 +104,7 @@ void free_instance(BInst<T>* I) {
   if (I->own) {
     hfree(I->ws);
     hfree(I->part);
+    hfree(I->bed);
     if (I->disc) bsw_disc_destroy(I->disc);
     if (I->mesh) bsw_mesh_destroy(I->mesh);
   }
@@ -943,6 +946,7 @@ struct Request {
   std::vector<unsigned char> W0;  // optional initial state (host copy)
   bsw_params prm{};
   bsw_ic ic{};
+  bsw_bed bed{};
   bsw_solve_opts opt{};
   std::vector<unsigned char> W;   // result (host copy)
   bsw_solve_stats st{};
@@ -976,6 +980,12 @@ struct EngineImpl final : EngineIf {
     int rc = bsw_mesh_upload(c, 2, r->n_vert, r->xy.data(), r->n_el, r->e2v.data(), &I->mesh);
     if (!rc) rc = bsw_disc_create(I->mesh, r->P, r->precision, &I->disc);
     if (!rc) rc = check_params(I->disc, &I->prm);
+    if (!rc && r->bed.kind != BSW_BED_FLAT) {
+      if (hipMalloc((void**)&I->bed, sizeof(T) * (size_t)n_modes(2, r->P) * r->n_el) != hipSuccess)
+        rc = fail(c, BSW_E_OOM, "bed coefficients");
+      if (!rc) rc = bsw_bed_interpolate(I->disc, &r->bed, I->bed);
+      if (!rc) rc = bsw_disc_set_bed(I->disc, I->bed);
+    }
     if (!rc) rc = e.add(I, r->W0.empty() ? nullptr : r->W0.data(), 0, &r->ic);
     if (rc) {
       err = c->err;
@@ -1203,6 +1213,10 @@ int check_request(bsw_ctx c, const bsw_solve_request* q) {
     return fail(c, BSW_E_ARG, "need g, rho, gamma, beta > 0 and eta, sigma0 >= 0");
   if (p->reg != 3 && p->sigma0 > 0 && p->sigma0 < 0.5 / p->beta)
     return fail(c, BSW_E_ARG, "regularisations 1 and 2 need sigma0 >= 1/(2 beta)");
+  const bsw_bed& b = q->bed;
+  if (b.kind < BSW_BED_FLAT || b.kind > BSW_BED_GAUSS || (b.kind != BSW_BED_FLAT && (b.order < 0 || b.order > q->P)) ||
+      (b.kind == BSW_BED_GAUSS && !(b.d > 0)))
+    return fail(c, BSW_E_ARG, "bad bed (kind, order 0..P, GAUSS d > 0)");
   return BSW_OK;
 }
 }  // namespace
@@ -1266,6 +1280,7 @@ int bsw_solve_submit(bsw_server S, const bsw_solve_request* q, uint64_t* ticket)
   }
   r->prm = q->params;
   r->ic = q->ic;
+  r->bed = q->bed;
   r->opt = q->opts;
   r->footprint = bsw_request_footprint(q);
   if (r->footprint > (int64_t)S->budget) return fail(S->user, BSW_E_ARG, "request footprint exceeds the server budget");

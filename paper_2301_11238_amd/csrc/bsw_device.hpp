@@ -74,6 +74,7 @@ struct MeshView {
   const T* hlen;     // [NFC][n_el] : face length / 2 (2-D), 1 (1-D)
   const int* nbr;    // [NFC][n_el] : 4*neighbour + neighbour's local face, -1 on the boundary
   const double* vert;  // [(D+1)*D][n_el] vertex coordinates (FP64)
+  const T* bed;        // [NP][n_el] modal coefficients of the bed H; nullptr = flat bed
 };
 
 template <class T> __device__ __forceinline__ T dsqrt(T x);

@@ -123,13 +123,43 @@ __device__ __forceinline__ void contract_volume(const Tab<D, P, T>& tb, int q, c
   }
 }
 
+// Momentum source of Eq. Sterm per unit depth at volume point q: S_b = -sl_b h
+// with sl_b = g_s [b = 0] + g_c dH/dx_b.  The bed gradient comes from the
+// element's bed coefficients and the affine metric.
+template <int D, int P, class T>
+__device__ __forceinline__ void source_slope(const Tab<D, P, T>& tb, int q, const Geo<D, T>& g, const MeshView<T>& m,
+                                             const DevParams<T>& p, int e, T (&sl)[D]) {
+  sl[0] = p.gs;
+#pragma unroll
+  for (int b = 1; b < D; ++b) sl[b] = T(0);
+  if (m.bed) {
+    T dr[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) dr[r] = T(0);
+#pragma unroll
+    for (int i = 0; i < Shape<D, P>::NP; ++i) {
+      const T Hi = m.bed[(size_t)i * m.n_el + e];
+#pragma unroll
+      for (int r = 0; r < D; ++r) dr[r] += tb.dphi[q][i][r] * Hi;
+    }
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      T v = T(0);
+#pragma unroll
+      for (int r = 0; r < D; ++r) v += g.xi[r][b] * dr[r];
+      sl[b] += p.gc * v;
+    }
+  }
+}
+
 // Pointwise volume integrand of Eq. WeakForm7 at one point (weight wq):
 // balance rows: A = wq (U/dt - S), B[r] = -wq sum_a xi_ra (F_a - Q_a);
 // gradient rows (c = b*D + a): CE = wq E_ab, CB[r] = wq xi_ra u_b.
+// sl is the source slope of the point (source_slope).
 template <int D, class T>
 __device__ __forceinline__ void volume_integrand(const DevParams<T>& p, const Geo<D, T>& g, T wq, const Pt<D, T>& s,
-                                                 const Stress<D, T>& st, T (&A)[1 + D], T (&B)[D][1 + D],
-                                                 T (&CE)[D * D], T (&CB)[D][D * D]) {
+                                                 const Stress<D, T>& st, const T (&sl)[D], T (&A)[1 + D],
+                                                 T (&B)[D][1 + D], T (&CE)[D * D], T (&CB)[D][D * D]) {
   T G[D][1 + D];  // F_a - Q_a
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -141,7 +171,7 @@ __device__ __forceinline__ void volume_integrand(const DevParams<T>& p, const Ge
   }
   A[0] = wq * s.h * p.inv_dt;
 #pragma unroll
-  for (int b = 0; b < D; ++b) A[1 + b] = wq * (s.h * s.u[b] * p.inv_dt + (b == 0 ? p.gs * s.h : T(0)));
+  for (int b = 0; b < D; ++b) A[1 + b] = wq * (s.h * s.u[b] * p.inv_dt + sl[b] * s.h);
 #pragma unroll
   for (int r = 0; r < D; ++r)
 #pragma unroll
@@ -166,8 +196,8 @@ __device__ __forceinline__ void volume_integrand(const DevParams<T>& p, const Ge
 template <int D, class T>
 __device__ __forceinline__ void volume_integrand_tan(const DevParams<T>& p, const Geo<D, T>& g, T wq,
                                                      const Pt<D, T>& s, const Stress<D, T>& st, const Pt<D, T>& ds,
-                                                     T (&A)[1 + D], T (&B)[D][1 + D], T (&CE)[D * D],
-                                                     T (&CB)[D][D * D]) {
+                                                     const T (&sl)[D], T (&A)[1 + D], T (&B)[D][1 + D],
+                                                     T (&CE)[D * D], T (&CB)[D][D * D]) {
   T dsig[D][D];
   stress_tan<D, T>(st, ds.E, dsig);
   T G[D][1 + D];
@@ -184,7 +214,7 @@ __device__ __forceinline__ void volume_integrand_tan(const DevParams<T>& p, cons
   A[0] = wq * ds.h * p.inv_dt;
 #pragma unroll
   for (int b = 0; b < D; ++b)
-    A[1 + b] = wq * ((ds.h * s.u[b] + s.h * ds.u[b]) * p.inv_dt + (b == 0 ? p.gs * ds.h : T(0)));
+    A[1 + b] = wq * ((ds.h * s.u[b] + s.h * ds.u[b]) * p.inv_dt + sl[b] * ds.h);
 #pragma unroll
   for (int r = 0; r < D; ++r)
 #pragma unroll
@@ -393,6 +423,8 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
         stress<D, T>(p, s.E, st);
         T A[1 + D], Bm[D][1 + D], CE[D * D], CB[D][D * D];
         const T wq = tb.qw[q] * g.detJ;
+        T sl[D];
+        source_slope<D, P, T>(tb, q, g, m, p, e, sl);
         if constexpr (TAN) {
           T dX[S::NF];
 #pragma unroll
@@ -404,9 +436,9 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
           }
           Pt<D, T> ds;
           unpack<D, T>(dX, ds);
-          volume_integrand_tan<D, T>(p, g, wq, s, st, ds, A, Bm, CE, CB);
+          volume_integrand_tan<D, T>(p, g, wq, s, st, ds, sl, A, Bm, CE, CB);
         } else {
-          volume_integrand<D, T>(p, g, wq, s, st, A, Bm, CE, CB);
+          volume_integrand<D, T>(p, g, wq, s, st, sl, A, Bm, CE, CB);
         }
 #pragma unroll
         for (int f = 0; f <= D; ++f) sV[q][B::OA + f][el] = A[f];
@@ -544,7 +576,9 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
     Stress<D, T> st;
     stress<D, T>(p, s.E, st);
     T A[1 + D], B[D][1 + D], CE[D * D], CB[D][D * D];
-    volume_integrand_tan<D, T>(p, g, tb.qw[q] * g.detJ, s, st, ds, A, B, CE, CB);
+    T sl[D];
+    source_slope<D, P, T>(tb, q, g, m, p, e, sl);
+    volume_integrand_tan<D, T>(p, g, tb.qw[q] * g.detJ, s, st, ds, sl, A, B, CE, CB);
     contract_volume<D, P, T>(tb, q, A, B, CE, CB, acc);
   }
 #pragma unroll 1

@@ -57,6 +57,7 @@ struct bsw_disc_s {
   RefElement ref;
   int bs = 0;
   size_t wsize = 0;  // bytes per real
+  const void* bed = nullptr;   // bed coefficients [n_p][n_el] (caller's device memory), nullptr = flat
   // linearisation
   const void* lin_W = nullptr;
   bsw_params lin_prm{};
@@ -152,6 +153,7 @@ MeshView<T> view(bsw_disc d) {
   v.dxi = dm->dxi; v.detJ = dm->detJ; v.nrm = dm->nrm; v.hlen = dm->hlen;
   v.nbr = d->mesh->nbr;
   v.vert = d->mesh->vert;
+  v.bed = (const T*)d->bed;
   return v;
 }
 
@@ -353,6 +355,7 @@ __device__ void ic_eval(const bsw_ic& ic, int dim, double x, double y, double& h
     } break;
     case BSW_IC_SINE_U: h = ic.a; u = ic.b * sin(pi * x / ic.L); break;
     case BSW_IC_LINEAR_X: h = ic.a + ic.b * x; break;
+    case BSW_IC_SURFACE: h = ic.a + ic.b * x; break;  // the bed is subtracted after the projection
     case BSW_IC_SHEAR_Y: h = ic.a; u = ic.b * cos(pi * y / ic.L); break;
     case BSW_IC_VORTEX:
       h = ic.a;
@@ -401,10 +404,15 @@ __global__ void __launch_bounds__(256) k_project_ic(T* __restrict__ W, MeshView<
       for (int f = 0; f <= D; ++f) acc[f][i] += c * val[f];
     }
   }
-  // positivity of the projected depth: where it drops below a tenth of the
-  // element mean at a volume or face point, scale the higher depth modes so
-  // the minimum is a tenth of the mean (mean and mass unchanged)
-  {
+  if (ic.kind == BSW_IC_SURFACE) {
+    // h = surface - H mode by mode: as continuous as the bed
+    if (m.bed)
+#pragma unroll
+      for (int i = 0; i < S::NP; ++i) acc[0][i] -= (double)m.bed[(size_t)i * n + e];
+  } else {
+    // positivity of the projected depth: where it drops below a tenth of the
+    // element mean at a volume or face point, scale the higher depth modes so
+    // the minimum is a tenth of the mean (mean and mass unchanged)
     const double mean = acc[0][0] * (double)tb.phi[0][0];
     double mn = INFINITY;
     for (int q = 0; q < S::NQ; ++q) {
@@ -427,6 +435,59 @@ __global__ void __launch_bounds__(256) k_project_ic(T* __restrict__ W, MeshView<
   for (int f = 0; f < S::NF; ++f)
 #pragma unroll
     for (int i = 0; i < S::NP; ++i) W[(size_t)(f * S::NP + i) * n + e] = f <= D ? (T)acc[f][i] : T(0);
+}
+
+// Bed interpolant (Eq. Sterm, Sec. 5): H at the NN order-m0 nodes of element e
+// (reference coordinates xi[2k], xi[2k+1], FP64), then the modal coefficients
+// c = Vinv H(nodes) of the first NN modes; the higher modes are zero.
+__device__ double bed_eval(const bsw_bed& b, int dim, double x, double y) {
+  switch (b.kind) {
+    case BSW_BED_COS: return b.a * cos(b.kx * x) * (dim == 2 ? cos(b.ky * y) : 1.0);
+    case BSW_BED_GAUSS: {
+      const double r2 = (x - b.x0) * (x - b.x0) + (dim == 2 ? (y - b.y0) * (y - b.y0) : 0.0);
+      return b.a * exp(-r2 / b.d);
+    }
+    default: return 0.0;
+  }
+}
+
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) k_bed_interp(T* __restrict__ H, MeshView<T> m, bsw_bed bed, int nn,
+                                                     const double* __restrict__ tab) {
+  using S = Shape<D, P>;
+  const int n = m.n_el;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double* xi = tab;             // [nn][2]
+  const double* vinv = tab + 2 * nn;  // [nn][nn], row = mode
+  double vx[D + 1][D];
+#pragma unroll
+  for (int k = 0; k <= D; ++k)
+#pragma unroll
+    for (int a = 0; a < D; ++a) vx[k][a] = m.vert[(size_t)(k * D + a) * n + e];
+  double hv[S::NP];
+#pragma unroll
+  for (int j = 0; j < S::NP; ++j) {
+    hv[j] = 0.0;
+    if (j < nn) {
+      double x, y = 0.0;
+      if (D == 1) {
+        x = vx[0][0] + 0.5 * (xi[2 * j] + 1.0) * (vx[1][0] - vx[0][0]);
+      } else {
+        const double s = xi[2 * j], t = xi[2 * j + 1];
+        x = vx[0][0] + s * (vx[1][0] - vx[0][0]) + t * (vx[D][0] - vx[0][0]);
+        y = vx[0][D - 1] + s * (vx[1][D - 1] - vx[0][D - 1]) + t * (vx[D][D - 1] - vx[0][D - 1]);
+      }
+      hv[j] = bed_eval(bed, D, x, y);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < S::NP; ++i) {
+    double c = 0.0;
+    if (i < nn)
+      for (int j = 0; j < nn; ++j) c += vinv[i * nn + j] * hv[j];
+    H[(size_t)i * n + e] = (T)c;
+  }
 }
 
 // ---------------------------------------------------------------- reductions (host helpers)
@@ -567,6 +628,73 @@ struct ICLaunch {
     return BSW_OK;
   }
 };
+
+struct BedLaunch {
+  bsw_disc d; bsw_bed bed; void* H; int nn; double* tab;
+  template <int D, int P, class T>
+  int operator()() {
+    auto m = view<T>(d);
+    hipLaunchKernelGGL((k_bed_interp<D, P, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream, (T*)H, m, bed, nn,
+                       tab);
+    HIPCHK(d->mesh->ctx, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+// Order-m interpolation nodes shared by neighbouring elements, as reference
+// coordinates: Gauss-Lobatto points on [-1, 1]; on the unit triangle the
+// vertices, each edge's interior Gauss-Lobatto points (symmetric about the
+// edge midpoint, so both elements of an edge meet the same physical points)
+// and the centroid at m = 3.
+bool bed_nodes(int dim, int m, std::vector<double>& xi) {
+  std::vector<double> t;  // interior Lobatto points: the roots of P_m'
+  if (m == 2) t = {0.0};
+  else if (m == 3) t = {-std::sqrt(0.2), std::sqrt(0.2)};
+  else if (m == 4) t = {-std::sqrt(3.0 / 7.0), 0.0, std::sqrt(3.0 / 7.0)};
+  else if (m != 1) return false;
+  xi.clear();
+  if (dim == 1) {
+    xi.insert(xi.end(), {-1.0, 0.0});
+    for (double v : t) xi.insert(xi.end(), {v, 0.0});
+    xi.insert(xi.end(), {1.0, 0.0});
+    return true;
+  }
+  if (m > 3) return false;
+  const double V[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+  for (auto& v : V) xi.insert(xi.end(), {v[0], v[1]});
+  for (int f = 0; f < 3; ++f)
+    for (double v : t) {
+      const double s = 0.5 * (v + 1.0);
+      const double* A = V[f];
+      const double* B = V[(f + 1) % 3];
+      xi.insert(xi.end(), {A[0] + s * (B[0] - A[0]), A[1] + s * (B[1] - A[1])});
+    }
+  if (m == 3) xi.insert(xi.end(), {1.0 / 3.0, 1.0 / 3.0});
+  return true;
+}
+
+// In-place inverse of a small dense matrix (Gauss-Jordan, partial pivoting).
+bool invert_small(int n, std::vector<double>& A) {
+  std::vector<double> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int pv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[i * n + k]) > std::fabs(A[pv * n + k])) pv = i;
+    if (A[pv * n + k] == 0.0) return false;
+    for (int j = 0; j < n; ++j) { std::swap(A[k * n + j], A[pv * n + j]); std::swap(I[k * n + j], I[pv * n + j]); }
+    const double inv = 1.0 / A[k * n + k];
+    for (int j = 0; j < n; ++j) { A[k * n + j] *= inv; I[k * n + j] *= inv; }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = A[i * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) { A[i * n + j] -= f * A[k * n + j]; I[i * n + j] -= f * I[k * n + j]; }
+    }
+  }
+  A.swap(I);
+  return true;
+}
 
 // ---------------------------------------------------------------- table staging
 template <int D, int P, class T>
@@ -813,6 +941,51 @@ int bsw_project_ic(bsw_disc d, const bsw_ic* ic, void* W) {
   (void)hipStreamSynchronize(c->stream);
   hfree(qxi);
   return rc;
+}
+
+int bsw_bed_interpolate(bsw_disc d, const bsw_bed* bed, void* H) {
+  if (!d || !bed || !H) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  bsw_ctx c = d->mesh->ctx;
+  const int dim = d->mesh->dim;
+  const int m = bed->order > 0 ? bed->order : d->P;
+  if (m < 1 || m > d->P) return fail(c, BSW_E_ARG, "bed order must be in 1..P");
+  if (bed->kind < BSW_BED_FLAT || bed->kind > BSW_BED_GAUSS) return fail(c, BSW_E_ARG, "unknown bed kind");
+  if (bed->kind == BSW_BED_GAUSS && !(bed->d > 0)) return fail(c, BSW_E_ARG, "GAUSS bed needs d > 0");
+  std::vector<double> xi;
+  if (!bed_nodes(dim, m, xi)) return fail(c, BSW_E_ARG, "bed order not supported for this element");
+  const int nn = (int)xi.size() / 2;
+  const int nm = dim == 1 ? m + 1 : (m + 1) * (m + 2) / 2;
+  if (nn != nm || nm > d->ref.np) return fail(c, BSW_E_ARG, "bed node count");
+  // Vandermonde of the first nm modes (they span the degree-m polynomials:
+  // both bases are ordered by total degree) at the nodes, inverted
+  std::vector<double> V((size_t)nn * nn), phi(d->ref.np);
+  for (int j = 0; j < nn; ++j) {
+    eval_basis(dim, d->P, xi[2 * j], xi[2 * j + 1], phi.data(), nullptr);
+    for (int k = 0; k < nn; ++k) V[(size_t)j * nn + k] = phi[k];
+  }
+  if (!invert_small(nn, V)) return fail(c, BSW_E_ARG, "singular bed interpolation nodes");
+  std::vector<double> host(xi);
+  host.insert(host.end(), V.begin(), V.end());
+  double* tab = nullptr;
+  if (int rc = dev_alloc(c, &tab, host.size())) return rc;
+  hipError_t he = hipMemcpyAsync(tab, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice, c->stream);
+  int rc = BSW_OK;
+  if (he != hipSuccess) {
+    rc = fail(c, BSW_E_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(he));
+  } else {
+    BedLaunch L{d, *bed, H, nn, tab};
+    rc = dispatch(d, L);
+  }
+  (void)hipStreamSynchronize(c->stream);
+  hfree(tab);
+  return rc;
+}
+
+int bsw_disc_set_bed(bsw_disc d, const void* H) {
+  if (!d) return fail(nullptr, BSW_E_ARG, "null discretisation");
+  d->bed = H;
+  d->lin_W = nullptr;  // the Jacobian depends on the bed
+  return BSW_OK;
 }
 
 int bsw_step_begin(bsw_disc d, const bsw_params* p, double dt, const void* Wold, void* bold) {

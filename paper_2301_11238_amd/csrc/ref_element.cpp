@@ -69,6 +69,24 @@ void line_basis(int P, double xi, double* phi, double* dphi) {
 
 void tri_basis(int P, double xi, double eta, double* phi, double* dphi) {
   const double om = 1.0 - eta;          // (1 - b) / 2
+  if (om == 0.0) {
+    // the collapsed vertex (0, 1): P_p(a) (1 - eta)^p tends to 0 for p >= 1
+    // (its homogeneous form is a polynomial in 2 xi + eta - 1 and 1 - eta,
+    // both zero here), and only p = 1 keeps a first derivative
+    int k = 0;
+    for (int n = 0; n <= P; ++n)
+      for (int q = 0; q <= n; ++q, ++k) {
+        const int p = n - q;
+        const double c = std::sqrt(2.0 * (2 * p + 1) * (p + q + 1));
+        const double gb = jacobi(q, 2.0 * p + 1, 0, 1.0), dgb = jacobi_d(q, 2.0 * p + 1, 0, 1.0);
+        phi[k] = p == 0 ? c * gb : 0.0;
+        if (dphi) {
+          dphi[2 * k] = p == 1 ? c * 2.0 * gb : 0.0;
+          dphi[2 * k + 1] = p == 1 ? c * gb : (p == 0 ? c * 2.0 * dgb : 0.0);
+        }
+      }
+    return;
+  }
   const double a = 2.0 * xi / om - 1.0;
   const double b = 2.0 * eta - 1.0;
   int k = 0;
