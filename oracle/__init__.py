@@ -97,6 +97,7 @@ def lib():
         L.or_diagnostics.argtypes = [C.c_void_p, C.POINTER(OrParams), dp, dp]
         L.or_bed_interpolate.argtypes = [C.c_void_p, C.POINTER(OrBed), dp]
         L.or_set_bed.argtypes = [C.c_void_p, dp]
+        L.or_set_orders.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
         L.or_eval_points.argtypes = [C.c_void_p, dp, dp]
         L.or_cfl_dt.restype = C.c_double
         L.or_cfl_dt.argtypes = [C.c_void_p, C.POINTER(OrParams), dp, C.c_double]
@@ -254,6 +255,11 @@ class Oracle:
         He = np.ascontiguousarray(np.asarray(H, dtype=np.float64).T)
         assert He.shape == (self.n_el, self.np)
         lib().or_set_bed(self.h, _dp(He))
+
+    def set_orders(self, m1: int, m2: int, m3: int) -> None:
+        """Orders of h, u and E (each 0..P; P is the storage order)."""
+        if lib().or_set_orders(self.h, int(m1), int(m2), int(m3)) != 0:
+            raise ValueError("orders must be in 0..P")
 
     # ------------------------------------------------------------- operator
     def step_begin(self, params, Wold, dt, bc=1):

@@ -21,7 +21,11 @@
  *     and the Newton / time loop (Sec. 5.1, Sec. 6: at most 10 iterations);
  *   - diagnostics: mass and the active-region percentage (Sec. 6);
  *   - a variable bed H (Eq. Sterm, Sec. 5: H given at order m0 <= P) by
- *     nodal interpolation that is continuous across faces.
+ *     nodal interpolation that is continuous across faces;
+ *   - mixed orders m1, m2, m3 for h, u and E (Sec. 5): with bases ordered by
+ *     total degree, field f lives in the span of its first N(m_f) modes and is
+ *     tested with them; the remaining modes carry the trivial equations
+ *     W = 0 (residual rows equal to the coefficient, identity Jacobian rows).
  *
  * Layout inside the oracle: per-element blocks W[e][f][i] (f = field,
  * i = mode).  Field order: h, u_1..u_d, then E_ab = d u_b / d x_a stored at
@@ -106,7 +110,15 @@ typedef struct {
   or_ref ref;
   or_mesh mesh;
   double *bed;           /* [n_el*np] modal coefficients of the bed H; NULL = flat */
+  int nmode[3];          /* modes used by h, u and E (orders m1, m2, m3) */
 } or_disc;
+
+/* 1 when row (f*np + i) of an element block is a mode above its field's order */
+static int row_unused(const or_disc* D, int row) {
+  int np = D->ref.np, f = row / np, i = row % np, dim = D->ref.dim;
+  int nm = f == 0 ? D->nmode[0] : (f <= dim ? D->nmode[1] : D->nmode[2]);
+  return i >= nm;
+}
 
 /* Legendre polynomial P_n and derivative by the three-term recursion. */
 static void legendre(int n, double x, double* p, double* dp) {
@@ -842,6 +854,7 @@ void* or_create(int dim, int P, int n_vert, const double* xy, int n_el, const in
   int rc = ref_build(&D->ref, dim, P);
   if (!rc) rc = mesh_build(D, dim, n_vert, xy, n_el, e2v);
   if (rc) { free(D); *err = rc; return NULL; }
+  D->nmode[0] = D->nmode[1] = D->nmode[2] = D->ref.np;
   *err = 0;
   return D;
 }
@@ -945,6 +958,8 @@ int or_residual(void* h, const or_params* p, double dt, const double* W, const d
     element_eval(D, p, dt, W, e, NULL, NULL, Re);
     for (int f = 0; f <= dim; ++f)
       for (int i = 0; i < np; ++i) Re[f * np + i] -= bold[(size_t)e * bs + f * np + i];
+    for (int k = 0; k < bs; ++k)
+      if (row_unused(D, k)) Re[k] = W[(size_t)e * bs + k];
   }
   return 0;
 }
@@ -961,6 +976,8 @@ int or_jac_apply(void* h, const or_params* p, double dt, const double* W, const 
       if (nb >= 0) vn[f] = x + (size_t)nb * bs;
     }
     element_eval(D, p, dt, W, e, vn, x + (size_t)e * bs, y + (size_t)e * bs);
+    for (int k = 0; k < bs; ++k)
+      if (row_unused(D, k)) y[(size_t)e * bs + k] = x[(size_t)e * bs + k];
   }
   return 0;
 }
@@ -975,7 +992,7 @@ int or_jac_blocks(void* h, const or_params* p, double dt, const double* W, doubl
     for (int j = 0; j < bs; ++j) {
       for (int k = 0; k < bs; ++k) v[k] = (k == j);
       element_eval(D, p, dt, W, e, NULL, v, col);
-      for (int i = 0; i < bs; ++i) B[i * bs + j] = col[i];
+      for (int i = 0; i < bs; ++i) B[i * bs + j] = row_unused(D, i) ? (double)(i == j) : col[i];
     }
   }
   return 0;
@@ -997,7 +1014,7 @@ int or_jac_offdiag(void* h, const or_params* p, double dt, const double* W, doub
       for (int j = 0; j < bs; ++j) {
         for (int k = 0; k < bs; ++k) v[k] = (k == j);
         element_eval(D, p, dt, W, e, vn, zero, col);
-        for (int i = 0; i < bs; ++i) B[i * bs + j] = col[i];
+        for (int i = 0; i < bs; ++i) B[i * bs + j] = row_unused(D, i) ? 0.0 : col[i];
       }
     }
   }
@@ -1246,9 +1263,12 @@ int or_project_ic(void* h, const or_ic* ic, double* W) {
        * equals it in coefficient space and h is as continuous as H */
       if (D->bed)
         for (int i = 0; i < np; ++i) We[i] -= D->bed[(size_t)e * np + i];
-    } else {
-      ic_positivity(R, We);
     }
+    /* fields of lower order keep their first N(m_f) modes (the L2 projection
+     * onto their space, the basis being orthonormal and hierarchical) */
+    for (int k = 0; k < bs; ++k)
+      if (row_unused(D, k)) We[k] = 0.0;
+    if (ic->kind != 8) ic_positivity(R, We);
   }
   return 0;
 }
@@ -1340,6 +1360,17 @@ int or_bed_interpolate(void* h, const or_bed* bed, double* H) {
     }
     lu_solve(nm, Vd, piv, c);
     for (int i = 0; i < np; ++i) H[(size_t)e * np + i] = i < nm ? c[i] : 0.0;
+  }
+  return 0;
+}
+
+/* Orders m1, m2, m3 of h, u and E (Sec. 5), each 0..P; P is the storage order. */
+int or_set_orders(void* h, int m1, int m2, int m3) {
+  or_disc* D = h;
+  int m[3] = {m1, m2, m3};
+  for (int k = 0; k < 3; ++k) {
+    if (m[k] < 0 || m[k] > D->ref.P) return -1;
+    D->nmode[k] = D->ref.dim == 1 ? m[k] + 1 : (m[k] + 1) * (m[k] + 2) / 2;
   }
   return 0;
 }
