@@ -197,6 +197,23 @@ int bsw_bed_interpolate(bsw_disc disc, const bsw_bed* bed, void* H);
  * again (BSW_E_STATE until then). */
 int bsw_disc_set_bed(bsw_disc disc, const void* H);
 
+/* ---------------------------------------------------------------- mixed orders (Sec. 5: m1, m2, m3) */
+/* Orders of h, u and E, each in 0..P (P, the discretisation's order, is the
+ * storage order and sets the quadrature rules; default m1 = m2 = m3 = P).
+ * With the degree-ordered bases, a field of order m keeps its first N(m)
+ * modes (N(m) = m + 1 in 1-D, (m + 1)(m + 2)/2 on triangles) and is tested
+ * with them.  The higher modes stay in W and carry the trivial equations
+ * W = 0: their residual rows equal the coefficient, their Jacobian rows are
+ * identity rows (in the diagonal blocks of bsw_jacobian_blocks and the
+ * preconditioner their columns are unit columns too, so solves keep them
+ * exactly zero), and bsw_project_ic zeroes them (the L2 projection onto the
+ * field's space, taken before the positivity scaling; for IC kind SURFACE
+ * after subtracting the bed).  A bed may have any order m0 <= P, above m1
+ * too (then the lake at rest is not exact, Sec. 6.1).  The Jacobian must be
+ * linearized again after a change (BSW_E_STATE until then).  BSW_E_ARG for
+ * orders outside 0..P. */
+int bsw_disc_set_orders(bsw_disc disc, int m1, int m2, int m3);
+
 /* ---------------------------------------------------------------- the operator */
 /* b_old[f][i][e] = (1/dt) <phi_i, U_f(W_old)>_e for f < 1+d: the old-time part
  * of the first term of Eq. WeakForm7 (U = (h, h u), Eq. Uterm). */
@@ -281,7 +298,8 @@ enum { BSW_REQ_QUEUED = 0, BSW_REQ_RUNNING = 1, BSW_REQ_DONE = 2, BSW_REQ_FAILED
  * is an initial state of n_f n_p n_el reals of the request's precision in the
  * SoA layout; when NULL the initial condition ic is projected.  bed (kind
  * BSW_BED_FLAT when zero-initialised) is interpolated as by bsw_bed_interpolate
- * into memory of the request and set before ic is projected. */
+ * into memory of the request and set before ic is projected; so are the
+ * orders m1, m2, m3 when mixed_orders is nonzero. */
 typedef struct {
   int64_t n_vert;
   const double* xy;
@@ -294,6 +312,8 @@ typedef struct {
   const void* W0;
   bsw_solve_opts opts;
   bsw_bed bed;
+  int32_t mixed_orders;    /* nonzero: the orders below apply (bsw_disc_set_orders) */
+  int32_t m1, m2, m3;
 } bsw_solve_request;
 
 /* Device bytes a request occupies while resident: state and 11 + gmres_m

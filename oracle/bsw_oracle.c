@@ -25,7 +25,9 @@
  *   - mixed orders m1, m2, m3 for h, u and E (Sec. 5): with bases ordered by
  *     total degree, field f lives in the span of its first N(m_f) modes and is
  *     tested with them; the remaining modes carry the trivial equations
- *     W = 0 (residual rows equal to the coefficient, identity Jacobian rows).
+ *     W = 0 (residual rows equal to the coefficient, identity Jacobian rows;
+ *     the assembled blocks also drop their columns, so those modes stay
+ *     exactly zero through Newton).
  *
  * Layout inside the oracle: per-element blocks W[e][f][i] (f = field,
  * i = mode).  Field order: h, u_1..u_d, then E_ab = d u_b / d x_a stored at
@@ -992,7 +994,8 @@ int or_jac_blocks(void* h, const or_params* p, double dt, const double* W, doubl
     for (int j = 0; j < bs; ++j) {
       for (int k = 0; k < bs; ++k) v[k] = (k == j);
       element_eval(D, p, dt, W, e, NULL, v, col);
-      for (int i = 0; i < bs; ++i) B[i * bs + j] = row_unused(D, i) ? (double)(i == j) : col[i];
+      for (int i = 0; i < bs; ++i)
+        B[i * bs + j] = (row_unused(D, i) || row_unused(D, j)) ? (double)(i == j) : col[i];
     }
   }
   return 0;
@@ -1014,7 +1017,7 @@ int or_jac_offdiag(void* h, const or_params* p, double dt, const double* W, doub
       for (int j = 0; j < bs; ++j) {
         for (int k = 0; k < bs; ++k) v[k] = (k == j);
         element_eval(D, p, dt, W, e, vn, zero, col);
-        for (int i = 0; i < bs; ++i) B[i * bs + j] = row_unused(D, i) ? 0.0 : col[i];
+        for (int i = 0; i < bs; ++i) B[i * bs + j] = (row_unused(D, i) || row_unused(D, j)) ? 0.0 : col[i];
       }
     }
   }

@@ -63,7 +63,8 @@ class SolveStats(C.Structure):
 class SolveRequest(C.Structure):
     _fields_ = [("n_vert", C.c_int64), ("xy", C.POINTER(C.c_double)), ("n_el", C.c_int64),
                 ("el2vert", C.POINTER(C.c_int32)), ("P", C.c_int32), ("precision", C.c_int32),
-                ("params", Params), ("ic", IC), ("W0", C.c_void_p), ("opts", SolveOpts), ("bed", Bed)]
+                ("params", Params), ("ic", IC), ("W0", C.c_void_p), ("opts", SolveOpts), ("bed", Bed),
+                ("mixed_orders", C.c_int32), ("m1", C.c_int32), ("m2", C.c_int32), ("m3", C.c_int32)]
 
 
 BSW_REQ_QUEUED, BSW_REQ_RUNNING, BSW_REQ_DONE, BSW_REQ_FAILED, BSW_REQ_CANCELLED = range(5)
@@ -84,6 +85,7 @@ SIGNATURES = {
     "bsw_project_ic": (C.c_int, [_VP, C.POINTER(IC), _VP]),
     "bsw_bed_interpolate": (C.c_int, [_VP, C.POINTER(Bed), _VP]),
     "bsw_disc_set_bed": (C.c_int, [_VP, _VP]),
+    "bsw_disc_set_orders": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int]),
     "bsw_step_begin": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP, _VP]),
     "bsw_operator_apply": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP, _VP, _VP]),
     "bsw_jacobian_linearize": (C.c_int, [_VP, C.POINTER(Params), C.c_double, _VP]),
@@ -296,6 +298,10 @@ class Disc:
         self._ck(lib().bsw_bed_interpolate(self.h, C.byref(make_bed(bed)), _ptr(H)))
         return H[0] if H.dim() == 3 else H
 
+    def set_orders(self, m1: int, m2: int, m3: int):
+        """Orders of h, u and E (each 0..P; P is the storage order)."""
+        self._ck(lib().bsw_disc_set_orders(self.h, int(m1), int(m2), int(m3)))
+
     def set_bed(self, H):
         """Bed coefficients [N_p, n_el] (device tensor kept by reference), or None."""
         self._bed = H
@@ -363,7 +369,7 @@ class Disc:
 class _ReqArrays:
     """Keeps the host arrays of a request alive until it is submitted."""
 
-    def __init__(self, xy, el2vert, P, precision, params, ic, opts, W0=None, bed=None):
+    def __init__(self, xy, el2vert, P, precision, params, ic, opts, W0=None, bed=None, orders=None):
         import numpy as np
         self.xy = np.ascontiguousarray(xy, dtype=np.float64)
         self.e2v = np.ascontiguousarray(el2vert, dtype=np.int32)
@@ -382,6 +388,9 @@ class _ReqArrays:
         r.W0 = C.c_void_p(self.W0.ctypes.data) if self.W0 is not None else None
         r.opts = opts.c()
         r.bed = make_bed(bed)
+        if orders is not None:
+            r.mixed_orders = 1
+            r.m1, r.m2, r.m3 = (int(m) for m in orders)
         self.req = r
 
 
@@ -416,9 +425,9 @@ class Server:
             pass
 
     def submit(self, xy, el2vert, P: int, precision: int, params: Params, ic=None, opts: Options = None,
-               W0=None, bed=None) -> int:
+               W0=None, bed=None, orders=None) -> int:
         opts = opts or Options()
-        a = _ReqArrays(xy, el2vert, P, precision, params, ic, opts, W0, bed)
+        a = _ReqArrays(xy, el2vert, P, precision, params, ic, opts, W0, bed, orders)
         t = C.c_uint64(0)
         self.ctx._check(lib().bsw_solve_submit(self.h, C.byref(a.req), C.byref(t)), self.ctx.h)
         n_p = (P + 1) * (P + 2) // 2

@@ -947,6 +947,7 @@ struct Request {
   bsw_params prm{};
   bsw_ic ic{};
   bsw_bed bed{};
+  int orders[3] = {-1, -1, -1};  // m1, m2, m3 (-1: the uniform order P)
   bsw_solve_opts opt{};
   std::vector<unsigned char> W;   // result (host copy)
   bsw_solve_stats st{};
@@ -980,6 +981,7 @@ struct EngineImpl final : EngineIf {
     int rc = bsw_mesh_upload(c, 2, r->n_vert, r->xy.data(), r->n_el, r->e2v.data(), &I->mesh);
     if (!rc) rc = bsw_disc_create(I->mesh, r->P, r->precision, &I->disc);
     if (!rc) rc = check_params(I->disc, &I->prm);
+    if (!rc && r->orders[0] >= 0) rc = bsw_disc_set_orders(I->disc, r->orders[0], r->orders[1], r->orders[2]);
     if (!rc && r->bed.kind != BSW_BED_FLAT) {
       if (hipMalloc((void**)&I->bed, sizeof(T) * (size_t)n_modes(2, r->P) * r->n_el) != hipSuccess)
         rc = fail(c, BSW_E_OOM, "bed coefficients");
@@ -1217,6 +1219,11 @@ int check_request(bsw_ctx c, const bsw_solve_request* q) {
   if (b.kind < BSW_BED_FLAT || b.kind > BSW_BED_GAUSS || (b.kind != BSW_BED_FLAT && (b.order < 0 || b.order > q->P)) ||
       (b.kind == BSW_BED_GAUSS && !(b.d > 0)))
     return fail(c, BSW_E_ARG, "bad bed (kind, order 0..P, GAUSS d > 0)");
+  if (q->mixed_orders) {
+    const int m[3] = {q->m1, q->m2, q->m3};
+    for (int k = 0; k < 3; ++k)
+      if (m[k] < 0 || m[k] > q->P) return fail(c, BSW_E_ARG, "orders m1, m2, m3 must be in 0..P");
+  }
   return BSW_OK;
 }
 }  // namespace
@@ -1281,6 +1288,11 @@ int bsw_solve_submit(bsw_server S, const bsw_solve_request* q, uint64_t* ticket)
   r->prm = q->params;
   r->ic = q->ic;
   r->bed = q->bed;
+  if (q->mixed_orders) {
+    r->orders[0] = q->m1;
+    r->orders[1] = q->m2;
+    r->orders[2] = q->m3;
+  }
   r->opt = q->opts;
   r->footprint = bsw_request_footprint(q);
   if (r->footprint > (int64_t)S->budget) return fail(S->user, BSW_E_ARG, "request footprint exceeds the server budget");

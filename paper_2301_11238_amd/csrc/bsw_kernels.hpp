@@ -80,6 +80,18 @@ __device__ __forceinline__ void load_trace(const T* __restrict__ tr, int n, int 
   for (int f = 0; f < S::NF; ++f) X[f] = tr[(size_t)(f * NFP + kp) * n + nb];
 }
 
+// Mixed orders (Sec. 5: m1, m2, m3 for h, u and E).  The bases are ordered by
+// total degree, so field f of order m lives in the span of its first N(m)
+// modes and is tested with them; the rows of the higher modes carry the
+// trivial equations W = 0 (residual row = coefficient, identity Jacobian row).
+// The diagonal blocks also drop those modes' columns, so the preconditioner
+// keeps them exactly zero.
+template <int D, class T>
+__device__ __forceinline__ bool row_unused(const MeshView<T>& m, int f, int i) {
+  const int nm = f == 0 ? m.nmode[0] : (f <= D ? m.nmode[1] : m.nmode[2]);
+  return i >= nm;
+}
+
 template <int D, class T>
 struct Geo {
   T xi[D][D];  // d xi_r / d x_a
@@ -503,6 +515,13 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
     const int row = idx / B::EB, el = idx % B::EB, e = e0 + el;
     if (e >= n) continue;
     const int f = row / S::NP, i = row % S::NP;
+    if (row_unused<D, T>(m, f, i)) {
+      T v;
+      if constexpr (TAN) v = sX[row][el];
+      else v = sW[row][el];
+      out[(size_t)row * n + e] = v;
+      continue;
+    }
     T acc = T(0);
     if (f <= D) {
 #pragma unroll
@@ -642,7 +661,11 @@ __device__ __forceinline__ void jac_columns_elem(const T* __restrict__ W, const 
 #pragma unroll
   for (int f = 0; f < S::NF; ++f)
 #pragma unroll
-    for (int i = 0; i < S::NP; ++i) blk[(f * S::NP + i) * S::BS + col] = acc[f][i];
+    for (int i = 0; i < S::NP; ++i) {
+      const int row = f * S::NP + i;
+      const bool trivial = row_unused<D, T>(m, f, i) || row_unused<D, T>(m, col / S::NP, col % S::NP);
+      blk[row * S::BS + col] = trivial ? T(row == col ? 1 : 0) : acc[f][i];
+    }
 }
 
 template <int D, int P, class T>

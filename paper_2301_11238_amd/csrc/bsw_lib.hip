@@ -58,6 +58,7 @@ struct bsw_disc_s {
   int bs = 0;
   size_t wsize = 0;  // bytes per real
   const void* bed = nullptr;   // bed coefficients [n_p][n_el] (caller's device memory), nullptr = flat
+  int nmode[3] = {0, 0, 0};    // modes used by h, u and E (orders m1, m2, m3)
   // linearisation
   const void* lin_W = nullptr;
   bsw_params lin_prm{};
@@ -154,6 +155,7 @@ MeshView<T> view(bsw_disc d) {
   v.nbr = d->mesh->nbr;
   v.vert = d->mesh->vert;
   v.bed = (const T*)d->bed;
+  for (int k = 0; k < 3; ++k) v.nmode[k] = d->nmode[k];
   return v;
 }
 
@@ -404,12 +406,19 @@ __global__ void __launch_bounds__(256) k_project_ic(T* __restrict__ W, MeshView<
       for (int f = 0; f <= D; ++f) acc[f][i] += c * val[f];
     }
   }
-  if (ic.kind == BSW_IC_SURFACE) {
+  if (ic.kind == BSW_IC_SURFACE && m.bed) {
     // h = surface - H mode by mode: as continuous as the bed
-    if (m.bed)
 #pragma unroll
-      for (int i = 0; i < S::NP; ++i) acc[0][i] -= (double)m.bed[(size_t)i * n + e];
-  } else {
+    for (int i = 0; i < S::NP; ++i) acc[0][i] -= (double)m.bed[(size_t)i * n + e];
+  }
+  // fields of lower order keep their first N(m) modes: the L2 projection onto
+  // their space (orthonormal, degree-ordered basis)
+#pragma unroll
+  for (int f = 0; f <= D; ++f)
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i)
+      if (row_unused<D, T>(m, f, i)) acc[f][i] = 0.0;
+  if (ic.kind != BSW_IC_SURFACE) {
     // positivity of the projected depth: where it drops below a tenth of the
     // element mean at a volume or face point, scale the higher depth modes so
     // the minimum is a tenth of the mean (mean and mass unchanged)
@@ -875,6 +884,7 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
   d->wsize = precision == BSW_FP64 ? 8 : 4;
   if (!build_reference(M->dim, P, d->ref)) { delete d; return fail(c, BSW_E_ARG, "reference element"); }
   d->bs = d->ref.nf * d->ref.np;
+  d->nmode[0] = d->nmode[1] = d->nmode[2] = d->ref.np;
   // FP32 geometry view on first use
   if (precision == BSW_FP32 && !M->m32.dxi) {
     auto upf = [&](float** dst, const std::vector<double>& src) -> int {
@@ -979,6 +989,16 @@ int bsw_bed_interpolate(bsw_disc d, const bsw_bed* bed, void* H) {
   (void)hipStreamSynchronize(c->stream);
   hfree(tab);
   return rc;
+}
+
+int bsw_disc_set_orders(bsw_disc d, int m1, int m2, int m3) {
+  if (!d) return fail(nullptr, BSW_E_ARG, "null discretisation");
+  const int m[3] = {m1, m2, m3};
+  for (int k = 0; k < 3; ++k)
+    if (m[k] < 0 || m[k] > d->P) return fail(d->mesh->ctx, BSW_E_ARG, "orders must be in 0..P");
+  for (int k = 0; k < 3; ++k) d->nmode[k] = d->mesh->dim == 1 ? m[k] + 1 : (m[k] + 1) * (m[k] + 2) / 2;
+  d->lin_W = nullptr;  // the Jacobian's trivial rows moved
+  return BSW_OK;
 }
 
 int bsw_disc_set_bed(bsw_disc d, const void* H) {

@@ -166,10 +166,10 @@ def test_lake_at_rest_not_kept_for_m0_above_m1(oracle_mod, orders):
         assert st["capped"] == 0
         X0, X = o.eval_points(W0), o.eval_points(W)
         errs.append(max(np.abs(X[:, :, 0] - X0[:, :, 0]).max(), np.abs(X[:, :, 1]).max()))
-        # the unused modes stay zero through the solve (to the direct solver's rounding)
+        # the unused modes stay exactly zero through the solve
         top = max(np.abs(W[0, m1 + 1:]).max(initial=0), np.abs(W[1, m2 + 1:]).max(initial=0),
                   np.abs(W[2, m3 + 1:]).max(initial=0))
-        assert top <= 1e-15 * np.abs(W).max()
+        assert top == 0.0
     assert 1e-8 < errs[0] < 1e-1, errs
     assert errs[1] < errs[0] / 3.0, errs
 
@@ -188,5 +188,5 @@ def test_inviscid_dam_break_depth_does_not_depend_on_m3(oracle_mod):
         assert st["capped"] == 0
         res.append(W)
     assert np.abs(res[0][:2] - res[1][:2]).max() <= 1e-10 * np.abs(res[0][:2]).max()
-    assert np.abs(res[1][2, 1:]).max() <= 1e-15 * np.abs(res[1]).max()
+    assert np.all(res[1][2, 1:] == 0.0)
     assert np.abs(res[0][2, 1:]).max() > 1e-6
