@@ -304,10 +304,15 @@ def main():
     if not args.kernels_only and st["jac_apply_launches"] > 0:
         k = dict(bytes=k["bytes"], seconds=st["jac_apply_seconds"] / st["jac_apply_launches"])
     achieved = k["bytes"] / k["seconds"] / 1e9
+    # the element-tile shape the autotuner kept for this pass (Jacobian, FP64, P2, this size class)
+    tuned = [r for r in bsw.tile_table() if (r["dim"], r["P"], r["bytes"], r["mode"]) == (2, problem.P, 8, 1)
+             and r["size_class"] == int(math.floor(math.log2(n_el)))]
+    lanes = tuned[0]["lanes"] if tuned else 256
     roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES.get(dominant),
-            "kernel": "kb_trace<2,2,double> + kb_elem<2,2,double,1> (matrix-free Jacobian apply inside the "
-                      "solve: face traces of x, then the element pass)",
+            "kernel": f"kb_trace<2,{problem.P},double> + kb_elem<2,{problem.P},double,1,{lanes}> (matrix-free "
+                      "Jacobian apply inside the solve: face traces of x, then the element pass in the "
+                      "autotuned tile shape)",
             "bytes_per_launch": k["bytes"], "launch_seconds": k["seconds"],
             "launches_timed": st.get("jac_apply_launches", 0)}
     if args.kernels_only:
@@ -344,6 +349,11 @@ def main():
         "fp32_mixed": fp32 if not args.no_fp32 else None,
         "kernels": {name: {"ms": 1e3 * v["seconds"], "GB/s": v["bytes"] / v["seconds"] / 1e9}
                     for name, v in kern.items()},
+        "tile_autotuner": [{"pass": "jacobian" if r["mode"] else "residual",
+                            "precision": "f64" if r["bytes"] == 8 else "f32", "size_class": r["size_class"],
+                            "lanes": r["lanes"],
+                            "best_us": {str(n): round(v, 2) for n, v in r["best_us"].items()}}
+                           for r in bsw.tile_table() if r["dim"] == 2 and r["P"] == problem.P],
     }
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests, args.serve_steps)

@@ -273,6 +273,23 @@ int bsw_cfl_dt(bsw_disc disc, const bsw_params* prm, const void* W, double cfl, 
 int bsw_solve(bsw_disc disc, const bsw_params* prm, const bsw_solve_opts* opts, void* W,
               bsw_solve_stats* stats_out);
 
+/* ---------------------------------------------------------------- element-tile autotuner */
+/* The element pass of batched and whole solves (bsw_solve and the server)
+ * runs in one of three tile shapes: workgroups of 128, 256 or 512 lanes, each
+ * taking as many elements as it has lanes per (volume + face) point set.
+ * All shapes give the same bits.  Per (dimension, order, precision,
+ * residual or Jacobian pass, size class floor(log2 of the launch's element
+ * count)) the library times the first launches of every shape (HIP events,
+ * read without blocking) and keeps the fastest for the process.
+ * bsw_tile_policy: -1 autotune (default), 0/1/2 force 128/256/512 lanes;
+ * *previous (may be NULL) receives the old policy.  Process-wide. */
+int bsw_tile_policy(int policy, int* previous);
+/* Up to max_rows rows of 10 doubles (host): {dim, P, bytes per real, pass
+ * (0 residual, 1 Jacobian), size class, chosen lanes (-1 while measuring),
+ * best microseconds of the 128/256/512-lane shapes (-1 if not yet timed),
+ * timed launches}; *n_rows receives the number of table entries. */
+int bsw_tile_table(double* rows, int max_rows, int* n_rows);
+
 /* ---------------------------------------------------------------- solve server (batched, continuous) */
 /* A server owns a worker thread, its own HIP stream on the context's device
  * and a device-memory budget.  Submitted requests wait in a FIFO queue; between

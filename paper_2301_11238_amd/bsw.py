@@ -106,6 +106,8 @@ SIGNATURES = {
     "bsw_solve_fetch": (C.c_int, [_VP, C.c_uint64, _VP, C.POINTER(SolveStats)]),
     "bsw_solve_cancel": (C.c_int, [_VP, C.c_uint64]),
     "bsw_server_info": (C.c_int, [_VP, _DP]),
+    "bsw_tile_policy": (C.c_int, [C.c_int, C.POINTER(C.c_int)]),
+    "bsw_tile_table": (C.c_int, [_DP, C.c_int, C.POINTER(C.c_int)]),
 }
 
 _lib = None
@@ -392,6 +394,29 @@ class _ReqArrays:
             r.mixed_orders = 1
             r.m1, r.m2, r.m3 = (int(m) for m in orders)
         self.req = r
+
+
+def tile_policy(policy: int) -> int:
+    """-1: autotune the element-tile shape; 0/1/2: force 128/256/512 lanes.
+    Returns the previous policy."""
+    prev = C.c_int(0)
+    if lib().bsw_tile_policy(int(policy), C.byref(prev)) != BSW_OK:
+        raise BswError("tile policy must be -1, 0, 1 or 2")
+    return prev.value
+
+
+def tile_table() -> list:
+    """The autotuner's entries: one dict per (dim, P, precision, pass, size class)."""
+    import numpy as np
+    n = C.c_int(0)
+    lib().bsw_tile_table(None, 0, C.byref(n))
+    rows = np.zeros((max(n.value, 1), 10))
+    lib().bsw_tile_table(rows.ctypes.data_as(_DP), n.value, C.byref(n))
+    out = []
+    for r in rows[: n.value]:
+        out.append(dict(dim=int(r[0]), P=int(r[1]), bytes=int(r[2]), mode=int(r[3]), size_class=int(r[4]),
+                        lanes=int(r[5]), best_us={128: r[6], 256: r[7], 512: r[8]}, timed=int(r[9])))
+    return out
 
 
 def request_footprint(n_el: int, P: int, precision: int, gmres_m: int = 30) -> int:

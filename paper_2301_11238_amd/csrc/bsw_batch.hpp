@@ -40,6 +40,90 @@ constexpr int kBaseSlots = B_V0;
 int n_modes(int dim, int P) { return dim == 1 ? P + 1 : (P + 1) * (P + 2) / 2; }
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// ------------------------------------------------------------ tile autotuner
+// Picks the element-tile shape (workgroup size of the element pass, kTileNT)
+// per (dimension, order, precision, residual or Jacobian, size class).  The
+// first launches of a key rotate through the shapes; the caller brackets each
+// with a HIP event pair and hands the pair over once both are recorded.
+// Completed pairs are read without blocking (hipEventQuery) on later picks,
+// and once every shape has kTunerSamples timings the one with the smallest
+// is kept for the process.  All shapes compute the same bits, so the choice
+// never changes a result.  policy >= 0 forces one shape.  Engines on several
+// threads share the table under its mutex.
+constexpr int kTunerSamples = 3;
+
+struct TileTuner {
+  struct Entry {
+    int choice = -1, next = 0;
+    int n[kTileShapes] = {};
+    float best_ms[kTileShapes] = {};
+  };
+  struct Pending {
+    uint64_t key;
+    int v;
+    hipEvent_t a, b;
+  };
+  std::mutex mu;
+  std::map<uint64_t, Entry> tab;
+  std::vector<Pending> pend;
+  int policy = -1;
+
+  static uint64_t key(int dim, int P, int wbytes, int mode, int64_t n_el) {
+    int cls = 0;
+    while (cls < 40 && (int64_t(1) << (cls + 1)) <= n_el) ++cls;  // floor(log2 n_el)
+    return (uint64_t)dim | (uint64_t)P << 4 | (uint64_t)wbytes << 8 | (uint64_t)mode << 16 | (uint64_t)cls << 24;
+  }
+  void poll_locked() {
+    for (size_t k = 0; k < pend.size();) {
+      Pending& q = pend[k];
+      if (hipEventQuery(q.b) != hipSuccess) { ++k; continue; }
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+        Entry& E = tab[q.key];
+        if (E.n[q.v] == 0 || ms < E.best_ms[q.v]) E.best_ms[q.v] = ms;
+        ++E.n[q.v];
+        bool all = true;
+        for (int v = 0; v < kTileShapes; ++v) all = all && E.n[v] >= kTunerSamples;
+        if (all && E.choice < 0) {
+          int b = 0;
+          for (int v = 1; v < kTileShapes; ++v)
+            if (E.best_ms[v] < E.best_ms[b]) b = v;
+          E.choice = b;
+        }
+      }
+      (void)hipEventDestroy(q.a);
+      (void)hipEventDestroy(q.b);
+      pend[k] = pend.back();
+      pend.pop_back();
+    }
+  }
+  // the shape for the next launch of key; *measure tells whether the key is
+  // still being measured (then time the launch and call submit)
+  int pick(uint64_t k, bool* measure) {
+    std::lock_guard<std::mutex> lk(mu);
+    *measure = false;
+    if (policy >= 0) return policy;
+    poll_locked();
+    Entry& E = tab[k];
+    if (E.choice >= 0) return E.choice;
+    const int v = E.next;
+    E.next = (E.next + 1) % kTileShapes;
+    *measure = true;
+    return v;
+  }
+  // an event pair, both already recorded around a launch of shape v; the
+  // table owns and destroys them
+  void submit(uint64_t k, int v, hipEvent_t a, hipEvent_t b) {
+    std::lock_guard<std::mutex> lk(mu);
+    pend.push_back({k, v, a, b});
+  }
+};
+
+TileTuner& tile_tuner() {
+  static TileTuner t;
+  return t;
+}
+
 // Device bytes one resident instance takes: state and Krylov vectors,
 // diagonal blocks and their inverses, face traces, reduction partials, mesh.
 int64_t instance_bytes(int64_t n_el, int dim, int P, int precision, int M) {
@@ -114,7 +198,9 @@ void free_instance(BInst<T>* I) {
 template <class T>
 struct BatchEngine {
   bsw_ctx c = nullptr;
-  int dim = 2, P = 0, M = 30, EB = 1, BS = 1, NFNFC = 1;
+  int dim = 2, P = 0, M = 30, BS = 1, NFNFC = 1;
+  int EBv[kTileShapes] = {1, 1, 1};  // elements per element-pass workgroup, per tile shape
+  int eb_cur = 1;                    // the shape of the element launch being built
   BInst<T>* slots[kMaxBatch] = {};
   InstDesc<T>* d_desc = nullptr;  // device
   InstDesc<T>* h_desc = nullptr;  // pinned staging of the descriptors
@@ -137,7 +223,9 @@ struct BatchEngine {
   int init(bsw_ctx ctx, int dim_, int P_, int M_) {
     c = ctx; dim = dim_; P = P_; M = M_;
     auto fs = [&]<int D, int PP, class TT>() -> int {
-      EB = Blk<D, PP>::EB;
+      EBv[0] = Blk<D, PP, kTileNT[0]>::EB;
+      EBv[1] = Blk<D, PP, kTileNT[1]>::EB;
+      EBv[2] = Blk<D, PP, kTileNT[2]>::EB;
       BS = Shape<D, PP>::BS;
       NFNFC = Shape<D, PP>::NF * Shape<D, PP>::NFC;
       return BSW_OK;
@@ -168,7 +256,7 @@ struct BatchEngine {
   enum Kind { K_ETILE, K_E256, K_E1, K_ITEM, K_VEC, K_ONE, K_TRACE };
   int tiles_of(const BInst<T>* I, int kind) const {
     switch (kind) {
-      case K_ETILE: return (int)((I->n_el + EB - 1) / EB);
+      case K_ETILE: return (int)((I->n_el + eb_cur - 1) / eb_cur);
       case K_E256: return I->ntile_e;
       case K_E1: return (int)I->n_el;
       case K_ITEM: return (int)((BS * I->n_el + 255) / 256);
@@ -228,24 +316,59 @@ struct BatchEngine {
     ++launches;
     return dispatchT<T>(dim, P, f);
   }
-  // mode 0: out = R(W; b_old); mode 1: out = J x (each after the trace pass of its argument)
-  int elem(int mode, const std::vector<int>& L, int sW, int sX, int sOut) {
-    if (int rc = mode == 0 ? trace(L, sW, 1) : trace(L, sX, 2)) return rc;
+  // The element pass over L (mode 0: residual, 1: Jacobian product) in the
+  // tile shape the autotuner picks for this launch's size; t_stop (optional)
+  // is recorded by the launch itself when it completes.
+  int elem_pass(int mode, const std::vector<int>& L, const std::vector<int>* jv, int sW, int sX, int sOut,
+                hipEvent_t t_stop = nullptr) {
+    int64_t n_el = 0;
+    for (int k : L) n_el += slots[k]->n_el;
+    const uint64_t key = TileTuner::key(dim, P, (int)sizeof(T), mode, n_el);
+    bool measure = false;
+    const int v = tile_tuner().pick(key, &measure);
+    eb_cur = EBv[v];
     BatchSet S;
-    const int nt = build(S, L, K_ETILE);
+    const int nt = build(S, L, K_ETILE, jv);
     if (!nt) return BSW_OK;
+    hipEvent_t ta = nullptr, tb = nullptr;
+    if (measure && (hipEventCreate(&ta) != hipSuccess || hipEventCreate(&tb) != hipSuccess ||
+                    hipEventRecord(ta, c->stream) != hipSuccess)) {
+      if (ta) (void)hipEventDestroy(ta);
+      if (tb) (void)hipEventDestroy(tb);
+      ta = tb = nullptr;
+    }
     auto f = [&]<int D, int PP, class TT>() -> int {
-      if (mode == 0)
-        hipLaunchKernelGGL((kb_elem<D, PP, TT, 0>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sW, sX,
-                           (int)B_BOLD, sOut);
-      else
-        hipLaunchKernelGGL((kb_elem<D, PP, TT, 1>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sW, sX,
-                           (int)B_BOLD, sOut);
+      auto go = [&]<int NT>() {
+        if (mode == 0)
+          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 0, NT>), dim3(nt), dim3(NT), 0, c->stream, nullptr, t_stop, 0,
+                                d_desc, S, sW, sX, (int)B_BOLD, sOut);
+        else
+          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 1, NT>), dim3(nt), dim3(NT), 0, c->stream, nullptr, t_stop, 0,
+                                d_desc, S, sW, sX, (int)B_BOLD, sOut);
+      };
+      if (v == 0) go.template operator()<kTileNT[0]>();
+      else if (v == 1) go.template operator()<kTileNT[1]>();
+      else go.template operator()<kTileNT[2]>();
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
+    const int rc = dispatchT<T>(dim, P, f);
+    if (ta) {
+      if (rc == BSW_OK && hipEventRecord(tb, c->stream) == hipSuccess) {
+        tile_tuner().submit(key, v, ta, tb);
+      } else {
+        (void)hipEventDestroy(ta);
+        (void)hipEventDestroy(tb);
+      }
+    }
+    if (rc) return rc;
     ++launches;
-    return dispatchT<T>(dim, P, f);
+    return BSW_OK;
+  }
+  // mode 0: out = R(W; b_old); mode 1: out = J x (each after the trace pass of its argument)
+  int elem(int mode, const std::vector<int>& L, int sW, int sX, int sOut) {
+    if (int rc = mode == 0 ? trace(L, sW, 1) : trace(L, sX, 2)) return rc;
+    return elem_pass(mode, L, nullptr, sW, sX, sOut);
   }
   // traces of the linearisation state for all of L; diagonal blocks and their
   // inverses for the instances in B (a subset of L)
@@ -512,23 +635,15 @@ struct BatchEngine {
     if (int rc = dispatchT<T>(dim, P, fp)) return rc;
     // w = J z (face traces of z, then the element pass)
     nt = build(S, L, K_TRACE, jv);
-    BatchSet S2;
-    const int nt2 = build(S2, L, K_ETILE, jv);
     auto fj = [&]<int D, int PP, class TT>() -> int {
-      if (timing) {
-        hipExtLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, jt0[pa], nullptr, 0, d_desc,
-                              S, (int)B_Z, 2);
-        hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 1>), dim3(nt2), dim3(256), 0, c->stream, nullptr, jt1[pa], 0,
-                              d_desc, S2, (int)B_W, (int)B_Z, (int)B_BOLD, (int)B_WK);
-      } else {
-        hipLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_Z, 2);
-        hipLaunchKernelGGL((kb_elem<D, PP, TT, 1>), dim3(nt2), dim3(256), 0, c->stream, d_desc, S2, (int)B_W,
-                           (int)B_Z, (int)B_BOLD, (int)B_WK);
-      }
+      hipExtLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, timing ? jt0[pa] : nullptr,
+                            nullptr, 0, d_desc, S, (int)B_Z, 2);
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
     if (int rc = dispatchT<T>(dim, P, fj)) return rc;
+    if (int rc = elem_pass(1, L, jv, (int)B_W, (int)B_Z, (int)B_WK, timing ? jt1[pa] : nullptr)) return rc;
+    --launches;  // counted in the tick's nine
     // pass 1: h1 = V^T w
     nt = build(S, L, K_VEC, jv);
     hipLaunchKernelGGL((kb_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
@@ -1229,6 +1344,41 @@ int check_request(bsw_ctx c, const bsw_solve_request* q) {
 }  // namespace
 
 extern "C" {
+
+int bsw_tile_policy(int policy, int* previous) {
+  if (policy < -1 || policy >= kTileShapes) return fail(nullptr, BSW_E_ARG, "tile policy must be -1, 0, 1 or 2");
+  TileTuner& t = tile_tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (previous) *previous = t.policy;
+  t.policy = policy;
+  return BSW_OK;
+}
+
+int bsw_tile_table(double* rows, int max_rows, int* n_rows) {
+  if (!n_rows || (max_rows > 0 && !rows)) return fail(nullptr, BSW_E_ARG, "null argument");
+  TileTuner& t = tile_tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.poll_locked();
+  int n = 0;
+  for (const auto& kv : t.tab) {
+    if (n < max_rows) {
+      const uint64_t k = kv.first;
+      const TileTuner::Entry& E = kv.second;
+      double* r = rows + (size_t)n * 10;
+      r[0] = (double)(k & 15);
+      r[1] = (double)((k >> 4) & 15);
+      r[2] = (double)((k >> 8) & 255);
+      r[3] = (double)((k >> 16) & 255);
+      r[4] = (double)((k >> 24) & 255);
+      r[5] = E.choice >= 0 ? (double)kTileNT[E.choice] : -1.0;
+      for (int v = 0; v < kTileShapes; ++v) r[6 + v] = E.n[v] ? 1e3 * E.best_ms[v] : -1.0;
+      r[9] = (double)(E.n[0] + E.n[1] + E.n[2]);
+    }
+    ++n;
+  }
+  *n_rows = n;
+  return BSW_OK;
+}
 
 int64_t bsw_request_footprint(const bsw_solve_request* q) {
   if (!q || q->P < 1 || q->P > 3 || q->n_el < 1) return -1;

@@ -112,15 +112,16 @@ __global__ void __launch_bounds__(256) kb_trace(const InstDesc<T>* __restrict__ 
 
 // MODE 0: R = residual(W; b_old) with the traces in trA; MODE 1: y = J(W) x
 // with the traces of W in trL and of x in trX
-template <int D, int P, class T, int MODE>
-__global__ void __launch_bounds__(256) kb_elem(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW, int sX,
-                                                int sB, int sOut) {
+// NT: the element-tile shape (workgroup size), chosen by the autotuner
+template <int D, int P, class T, int MODE, int NT>
+__global__ void __launch_bounds__(NT) kb_elem(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW, int sX,
+                                               int sB, int sOut) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int ai = bset_find(A, b);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int j = A.jv[ai];
-  const int e0 = (b - A.tile0[ai]) * Blk<D, P>::EB;
-  elem_blocked_tile<D, P, T, MODE>(bslot(I, sW, j), MODE == 1 ? bslot(I, sX, j) : nullptr,
+  const int e0 = (b - A.tile0[ai]) * Blk<D, P, NT>::EB;
+  elem_blocked_tile<D, P, T, MODE, NT>(bslot(I, sW, j), MODE == 1 ? bslot(I, sX, j) : nullptr,
                                    MODE == 0 ? bslot(I, sB, j) : nullptr, bslot(I, sOut, j),
                                    MODE == 0 ? I.trA : I.trL, MODE == 1 ? I.trX : nullptr, I.m, I.p, e0);
 }

@@ -75,7 +75,7 @@ struct MeshView {
   const int* nbr;    // [NFC][n_el] : 4*neighbour + neighbour's local face, -1 on the boundary
   const double* vert;  // [(D+1)*D][n_el] vertex coordinates (FP64)
   const T* bed;        // [NP][n_el] modal coefficients of the bed H; nullptr = flat bed
-  int nmode[3];        // modes used by h, u and E (orders m1, m2, m3; NP when uniform)
+  int nmodes;          // modes used by h | u << 8 | E << 16 (orders m1, m2, m3; NP when uniform)
 };
 
 template <class T> __device__ __forceinline__ T dsqrt(T x);

@@ -86,10 +86,12 @@ __device__ __forceinline__ void load_trace(const T* __restrict__ tr, int n, int 
 // trivial equations W = 0 (residual row = coefficient, identity Jacobian row).
 // The diagonal blocks also drop those modes' columns, so the preconditioner
 // keeps them exactly zero.
+// (One packed word: choosing among three loaded fields by a runtime field
+// index would make the compiler address the descriptor in scratch memory.)
 template <int D, class T>
 __device__ __forceinline__ bool row_unused(const MeshView<T>& m, int f, int i) {
-  const int nm = f == 0 ? m.nmode[0] : (f <= D ? m.nmode[1] : m.nmode[2]);
-  return i >= nm;
+  const int sel = f == 0 ? 0 : (f <= D ? 8 : 16);
+  return i >= ((m.nmodes >> sel) & 255);
 }
 
 template <int D, class T>
@@ -374,13 +376,18 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // in LDS; then one lane per (element, output row) contracts it with the test
 // functions and writes the row.  This keeps every lane's live state to one
 // point (no register spills at P3 in FP64) and gives NQ + NFC*NFQ lanes per
-// element instead of one.
-template <int D, int P>
+// element instead of one.  NT is the workgroup size (the element-tile shape:
+// EB = NT / (NQ + NFC*NFQ) elements); every NT gives the same bits, the
+// autotuner picks the fastest per order, precision and size class.
+constexpr int kTileShapes = 3;
+constexpr int kTileNT[kTileShapes] = {128, 256, 512};
+
+template <int D, int P, int NT = 256>
 struct Blk {
   using S = Shape<D, P>;
   static constexpr int NFP = S::NFC * S::NFQ;                          // face points per element
   static constexpr int NPT = S::NQ + NFP;                              // point items per element
-  static constexpr int EB = 256 / NPT;                                 // elements per workgroup
+  static constexpr int EB = NT / NPT;                                  // elements per workgroup
   static constexpr int OA = 0;                                         // A[f]
   static constexpr int OB = 1 + D;                                     // B[r][f]
   static constexpr int OCE = OB + D * (1 + D);                         // CE[c]
@@ -391,13 +398,13 @@ struct Blk {
 
 // MODE 0: residual (x unused, bold subtracted); MODE 1: Jacobian product
 // along x (bold unused).  One tile: elements e0 .. e0+EB-1 of one mesh.
-template <int D, int P, class T, int MODE>
+template <int D, int P, class T, int MODE, int NT = 256>
 __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const T* __restrict__ x,
                                                   const T* __restrict__ bold, T* __restrict__ out,
                                                   const T* __restrict__ trW, const T* __restrict__ trX,
                                                   const MeshView<T>& m, const DevParams<T>& p, int e0) {
   using S = Shape<D, P>;
-  using B = Blk<D, P>;
+  using B = Blk<D, P, NT>;
   constexpr bool TAN = MODE == 1;
   const Tab<D, P, T>& tb = tab<D, P, T>();
   const int n = m.n_el;
@@ -407,7 +414,7 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
   __shared__ T sV[S::NQ][B::NVF][B::EB];
   __shared__ T sF[B::NFP][B::NFF][B::EB];
 
-  for (int idx = tid; idx < S::BS * B::EB; idx += 256) {
+  for (int idx = tid; idx < S::BS * B::EB; idx += NT) {
     const int row = idx / B::EB, el = idx % B::EB, e = e0 + el;
     sW[row][el] = e < n ? W[(size_t)row * n + e] : T(0);
     if constexpr (TAN) sX[row][el] = e < n ? x[(size_t)row * n + e] : T(0);
@@ -511,7 +518,7 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
   }
   __syncthreads();
 
-  for (int idx = tid; idx < S::BS * B::EB; idx += 256) {
+  for (int idx = tid; idx < S::BS * B::EB; idx += NT) {
     const int row = idx / B::EB, el = idx % B::EB, e = e0 + el;
     if (e >= n) continue;
     const int f = row / S::NP, i = row % S::NP;

@@ -155,7 +155,7 @@ MeshView<T> view(bsw_disc d) {
   v.nbr = d->mesh->nbr;
   v.vert = d->mesh->vert;
   v.bed = (const T*)d->bed;
-  for (int k = 0; k < 3; ++k) v.nmode[k] = d->nmode[k];
+  v.nmodes = d->nmode[0] | d->nmode[1] << 8 | d->nmode[2] << 16;
   return v;
 }
 
