@@ -344,6 +344,12 @@ def main():
                    "gmres_per_step": st["gmres_total"] / max(1, st["steps"]),
                    "capped_steps": st["capped"],
                    "applies_per_step": applies / max(1, st["steps"]),
+                   # per pipelined Arnoldi step (nine launches): host time to issue it and
+                   # host time blocked on its results; issue < step time means the launch
+                   # path is not the limit (the device is)
+                   "arnoldi_step_us": 1e6 * el / max(1.0, st["arnoldi_steps"]) if st["arnoldi_steps"] else None,
+                   "host_issue_us_per_arnoldi_step": 1e6 * st["host_issue_seconds"] / max(1.0, st["arnoldi_steps"]),
+                   "host_wait_us_per_arnoldi_step": 1e6 * st["host_wait_seconds"] / max(1.0, st["arnoldi_steps"]),
                    "dof_steps_per_s": n_dof * st["steps"] / el},
         "roofline": roof,
         "fp32_mixed": fp32 if not args.no_fp32 else None,

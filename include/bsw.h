@@ -144,6 +144,10 @@ typedef struct {
   double jac_apply_seconds;  /* summed HIP-event time of the Jacobian-apply launches (timing != 0) */
   double jac_apply_launches; /* launches that were timed */
   double queue_seconds;      /* served solves: submit to admission (seconds is admission to completion) */
+  double host_issue_seconds; /* timing != 0: host time spent issuing the pipelined Arnoldi steps
+                                (all launches of a step) ... */
+  double host_wait_seconds;  /* ... and blocked waiting for a step's results */
+  double arnoldi_steps;      /* timing != 0: Arnoldi steps issued and read */
 } bsw_solve_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -57,7 +57,9 @@ class SolveStats(C.Structure):
                 ("max_mass_drift", C.c_double), ("active_pct", C.c_double), ("t_end", C.c_double),
                 ("seconds", C.c_double), ("operator_applies", C.c_double),
                 ("jacobian_applies", C.c_double), ("jac_apply_seconds", C.c_double),
-                ("jac_apply_launches", C.c_double), ("queue_seconds", C.c_double)]
+                ("jac_apply_launches", C.c_double), ("queue_seconds", C.c_double),
+                ("host_issue_seconds", C.c_double), ("host_wait_seconds", C.c_double),
+                ("arnoldi_steps", C.c_double)]
 
 
 class SolveRequest(C.Structure):

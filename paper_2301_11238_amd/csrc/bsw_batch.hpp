@@ -598,6 +598,8 @@ struct BatchEngine {
   hipEvent_t jt0[2] = {nullptr, nullptr}, jt1[2] = {nullptr, nullptr};
   bool timing = false;
   double jac_seconds = 0.0, jac_launches = 0.0;
+  // host time issuing Arnoldi steps and waiting for them (timing mode)
+  double issue_seconds = 0.0, wait_seconds = 0.0, arnoldi_steps = 0.0;
 
   int ensure_events() {
     if (tick_ev[0]) return BSW_OK;
@@ -787,10 +789,17 @@ struct BatchEngine {
           sorted.jv.push_back(nxt.jv[a]);
         }
         nxt = sorted;
+        const auto h0 = std::chrono::steady_clock::now();
         if (int rc = launch_tick(nxt)) return rc;
+        if (timing) issue_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
       }
       if (!cur.mem.empty()) {
+        const auto h0 = std::chrono::steady_clock::now();
         HIPCHK(c, hipEventSynchronize(tick_ev[cur.parity]));
+        if (timing) {
+          wait_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
+          arnoldi_steps += 1;
+        }
         ++ticks;
         if (timing) {
           float ms = 0.f;
@@ -1582,6 +1591,7 @@ int solve_one(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, bs
   E->e.timing = o->timing != 0;
   E->e.jac_seconds = 0.0;
   E->e.jac_launches = 0.0;
+  E->e.issue_seconds = E->e.wait_seconds = E->e.arnoldi_steps = 0.0;
   int rc = BSW_OK;
   while (!I->finished())
     if ((rc = E->e.step_all())) break;
@@ -1596,6 +1606,9 @@ int solve_one(bsw_disc d, const bsw_params* p, const bsw_solve_opts* o, T* W, bs
   st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   st->jac_apply_seconds = E->e.jac_seconds;
   st->jac_apply_launches = E->e.jac_launches;
+  st->host_issue_seconds = E->e.issue_seconds;
+  st->host_wait_seconds = E->e.wait_seconds;
+  st->arnoldi_steps = E->e.arnoldi_steps;
   E->e.take(I->slot);
   delete I;
   return rc ? rc : st->status;
