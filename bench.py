@@ -30,7 +30,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
 # scaled by the same counters on a plain copy of known size; None until the
 # counters are taken on the current kernel.
-TRAFFIC_BYTES = {"jacobian_apply": 25365511.0}  # trace + element pass; counter summary under profiles/
+TRAFFIC_BYTES = {"jacobian_apply": 25376768.0}  # trace + element pass; counter summary under profiles/
 
 
 def parse():
@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=3,
                     help="time steps per served request (each draw's horizon is cut to this many steps)")
+    ap.add_argument("--tile-policy", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="element-tile shape: -1 autotune (default), 0/1/2 force 128/256/512 lanes "
+                         "(profiling runs repeat the shape the autotuner picked in the bench run)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solve: a 256 MiB device copy (counter calibration) and 20 launches of each hot "
                          "kernel, for rocprofv3 --pmc passes")
@@ -244,6 +247,7 @@ def main():
     if args.workload == "c3":
         args.kernels_only = True
     ctx = bsw.Context(0)
+    bsw.tile_policy(args.tile_policy)
     stream = ctx.stream
     mesh = bsw.Mesh(ctx, 2, problem.xy, problem.el2vert)
     disc = bsw.Disc(mesh, problem.P, bsw.BSW_FP64)

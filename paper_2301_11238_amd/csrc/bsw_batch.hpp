@@ -50,7 +50,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // is kept for the process.  All shapes compute the same bits, so the choice
 // never changes a result.  policy >= 0 forces one shape.  Engines on several
 // threads share the table under its mutex.
-constexpr int kTunerSamples = 3;
+constexpr int kTunerSamples = 5;
 
 struct TileTuner {
   struct Entry {
