@@ -39,7 +39,8 @@ class OrParams(C.Structure):
     _fields_ = [("g", C.c_double), ("rho", C.c_double), ("alpha", C.c_double),
                 ("eta", C.c_double), ("sigma0", C.c_double), ("gamma", C.c_double),
                 ("beta", C.c_double), ("reg", C.c_int32), ("bc", C.c_int32),
-                ("dir", C.c_double * MAXNF), ("jac_frozen", C.c_int32)]
+                ("dir", C.c_double * MAXNF), ("jac_frozen", C.c_int32),
+                ("dir_tag", (C.c_double * MAXNF) * 3)]
 
 
 class OrIC(C.Structure):
@@ -98,6 +99,7 @@ def lib():
         L.or_bed_interpolate.argtypes = [C.c_void_p, C.POINTER(OrBed), dp]
         L.or_set_bed.argtypes = [C.c_void_p, dp]
         L.or_set_orders.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.or_set_boundary.argtypes = [C.c_void_p, C.POINTER(C.c_int8)]
         L.or_eval_points.argtypes = [C.c_void_p, dp, dp]
         L.or_cfl_dt.restype = C.c_double
         L.or_cfl_dt.argtypes = [C.c_void_p, C.POINTER(OrParams), dp, C.c_double]
@@ -121,8 +123,9 @@ def _ip(a):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
 
 
-def make_params(params, bc: int = 1, dirichlet=None) -> OrParams:
-    """params: workloads.Params (or anything with the same attributes)."""
+def make_params(params, bc: int = 1, dirichlet=None, dirichlet_tags=None) -> OrParams:
+    """params: workloads.Params (or anything with the same attributes);
+    dirichlet_tags: up to three exterior states of Dirichlet tags 1..3."""
     p = OrParams()
     for k in ("g", "rho", "alpha", "eta", "sigma0", "gamma", "beta"):
         setattr(p, k, float(getattr(params, k)))
@@ -132,6 +135,9 @@ def make_params(params, bc: int = 1, dirichlet=None) -> OrParams:
     if dirichlet is not None:
         for i, v in enumerate(dirichlet):
             p.dir[i] = float(v)
+    for t, st in enumerate(dirichlet_tags or []):
+        for i, v in enumerate(st):
+            p.dir_tag[t][i] = float(v)
     return p
 
 
@@ -256,6 +262,23 @@ class Oracle:
         assert He.shape == (self.n_el, self.np)
         lib().or_set_bed(self.h, _dp(He))
 
+    def set_boundary(self, codes=None, dirichlet_tags=None) -> None:
+        """Boundary codes per local face ([n_el, n_faces] int8, kind | tag << 2:
+        kind 1 wall, 2 Neumann, 3 Dirichlet, 0 the bc argument of each call;
+        tag 1..3 selects dirichlet_tags[tag - 1], tag 0 the dirichlet argument).
+        None resets every face to the bc argument."""
+        if codes is None:
+            rc = lib().or_set_boundary(self.h, None)
+        else:
+            c = np.ascontiguousarray(codes, dtype=np.int8).reshape(self.n_el * self.nfc)
+            rc = lib().or_set_boundary(self.h, c.ctypes.data_as(C.POINTER(C.c_int8)))
+        if rc != 0:
+            raise ValueError("boundary codes must be in 0..15")
+        self._dir_tags = [list(t) for t in (dirichlet_tags or [])]
+
+    def _mp(self, params, bc=1, dirichlet=None):
+        return make_params(params, bc, dirichlet, getattr(self, "_dir_tags", None))
+
     def set_orders(self, m1: int, m2: int, m3: int) -> None:
         """Orders of h, u and E (each 0..P; P is the storage order)."""
         if lib().or_set_orders(self.h, int(m1), int(m2), int(m3)) != 0:
@@ -263,26 +286,26 @@ class Oracle:
 
     # ------------------------------------------------------------- operator
     def step_begin(self, params, Wold, dt, bc=1):
-        p = make_params(params, bc)
+        p = self._mp(params, bc)
         We = to_elem(Wold); b = np.zeros_like(We)
         lib().or_step_begin(self.h, C.byref(p), float(dt), _dp(We), _dp(b))
         return from_elem(b)
 
     def residual(self, params, W, bold, dt, bc=1, dirichlet=None):
-        p = make_params(params, bc, dirichlet)
+        p = self._mp(params, bc, dirichlet)
         We = to_elem(W); be = to_elem(bold); R = np.zeros_like(We)
         lib().or_residual(self.h, C.byref(p), float(dt), _dp(We), _dp(be), _dp(R))
         return from_elem(R)
 
     def jac_apply(self, params, W, x, dt, bc=1, dirichlet=None):
-        p = make_params(params, bc, dirichlet)
+        p = self._mp(params, bc, dirichlet)
         We = to_elem(W); xe = to_elem(x); y = np.zeros_like(We)
         lib().or_jac_apply(self.h, C.byref(p), float(dt), _dp(We), _dp(xe), _dp(y))
         return from_elem(y)
 
     def jac_blocks(self, params, W, dt, bc=1):
         """Diagonal blocks, [n_el, bs, bs] with row/col index f*N_p + i."""
-        p = make_params(params, bc)
+        p = self._mp(params, bc)
         We = to_elem(W); bs = self.nf * self.np
         B = np.zeros((self.n_el, bs, bs))
         lib().or_jac_blocks(self.h, C.byref(p), float(dt), _dp(We), _dp(B))
@@ -290,7 +313,7 @@ class Oracle:
 
     def jac_offdiag(self, params, W, dt, bc=1, dirichlet=None):
         """Face-coupling blocks dR_e/dW_nbr, [n_el, n_faces, bs, bs]."""
-        p = make_params(params, bc, dirichlet)
+        p = self._mp(params, bc, dirichlet)
         We = to_elem(W); bs = self.nf * self.np
         B = np.zeros((self.n_el, self.nfc, bs, bs))
         lib().or_jac_offdiag(self.h, C.byref(p), float(dt), _dp(We), _dp(B))
@@ -382,7 +405,7 @@ class Oracle:
         Newton system exactly (sparse LU); 'gmres' uses the C block-Jacobi
         GMRES(m) path (for meshes too large to factor)."""
         o = _opts(opts or SolveOptions())
-        p = make_params(params, bc, dirichlet)
+        p = self._mp(params, bc, dirichlet)
         We = to_elem(W); be = to_elem(bold)
         if linear == "direct":
             its, conv = self._newton_direct(p, We, be, dt, o)
@@ -399,7 +422,7 @@ class Oracle:
         on the initial state unless overridden, last step clipped to t_end).
         record: optional list receiving (step, newton_its, status) per step."""
         o = _opts(opts)
-        p = make_params(params, bc, dirichlet)
+        p = self._mp(params, bc, dirichlet)
         if linear != "direct":
             We = to_elem(W0); st = OrSolveStats()
             lib().or_solve(self.h, C.byref(p), C.byref(o), _dp(We), C.byref(st))
@@ -421,7 +444,7 @@ class Oracle:
         if opts.cont_steps >= 2:
             n = opts.cont_steps
             g0, g1 = float(opts.cont_gamma0), float(params.gamma)
-            stages = [make_params(dataclasses.replace(params, gamma=g0 + (i - 1) * (g1 - g0) / (n - 1)), bc,
+            stages = [self._mp(dataclasses.replace(params, gamma=g0 + (i - 1) * (g1 - g0) / (n - 1)), bc,
                                   dirichlet) for i in range(1, n + 1)]
         else:
             stages = [p]

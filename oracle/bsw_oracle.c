@@ -54,6 +54,7 @@ typedef struct {
   int32_t bc;       /* 1 wall, 2 Neumann, 3 Dirichlet (Sec. 5.2) */
   double dir[MAXNF]; /* Dirichlet exterior values (h, u..., E...) */
   int32_t jac_frozen; /* 1: the Jacobian holds S_L, S_R of the HLL flux fixed (Appendix A) */
+  double dir_tag[3][MAXNF]; /* Dirichlet exterior values of boundary tags 1..3 */
 } or_params;
 
 typedef struct {
@@ -105,6 +106,7 @@ typedef struct {
   double *flen;          /* [n_el*nfc] */
   double *xq;            /* [n_el*nq*2] physical volume points */
   double *vx;            /* [n_el*3*2] vertex coordinates */
+  int8_t *fbc;           /* [n_el*nfc] boundary code of each local face: kind | tag << 2 */
   double total_measure, hmin;
 } or_mesh;
 
@@ -378,6 +380,7 @@ static int mesh_build(or_disc* D, int dim, int n_vert, const double* xy, int n_e
   M->flen = malloc(sizeof(double) * n_el * nfc);
   M->xq = calloc((size_t)n_el * R->nq * 2, sizeof(double));
   M->vx = calloc((size_t)n_el * 6, sizeof(double));
+  M->fbc = calloc((size_t)n_el * nfc, sizeof(int8_t));
   M->total_measure = 0.0; M->hmin = 1e300;
   for (int e = 0; e < n_el; ++e) {
     const int32_t* v = e2v + (size_t)e * nvpe;
@@ -716,17 +719,20 @@ static void mirror_state(int dim, const double* n, const pstate* in, pstate* out
 
 /* Exterior state on a boundary face (Sec. 5.2, plus the mirror-wall reading:
  * h+ = h-, u+ = R u-, E+ = R E- R, so that the central fluxes give u.n = 0 and
- * zero tangential traction, and the HLL mass flux vanishes). */
-static void bc_exterior(const or_params* p, int dim, const double* n, const pstate* in,
+ * zero tangential traction, and the HLL mass flux vanishes).  code = the
+ * face's kind | tag << 2: kind 1 wall, 2 Neumann, 3 Dirichlet, 0 the
+ * parameters' bc; a Dirichlet face takes the state of its tag (0: dir). */
+static void bc_exterior(const or_params* p, int dim, const double* n, int code, const pstate* in,
                         pstate* out, const pstate* din, pstate* dout) {
-  if (p->bc == 1) {
+  int kind = (code & 3) ? (code & 3) : p->bc, tag = code >> 2;
+  if (kind == 1) {
     mirror_state(dim, n, in, out);
     if (din) mirror_state(dim, n, din, dout);
-  } else if (p->bc == 2) { /* homogeneous Neumann: V+ = V-, E+ = E- */
+  } else if (kind == 2) { /* homogeneous Neumann: V+ = V-, E+ = E- */
     *out = *in;
     if (din) *dout = *din;
   } else { /* Dirichlet: prescribed exterior values */
-    unpack(dim, p->dir, out);
+    unpack(dim, tag ? p->dir_tag[tag - 1] : p->dir, out);
     if (din) memset(dout, 0, sizeof(*dout));
   }
 }
@@ -815,7 +821,7 @@ static void element_eval(const or_disc* D, const or_params* p, double dt, const 
           else memset(&dsp, 0, sizeof(dsp));
         }
       } else {
-        bc_exterior(p, dim, n, &sm, &sp, tan ? &dsm : NULL, &dsp);
+        bc_exterior(p, dim, n, M->fbc[e * nfc + fc], &sm, &sp, tan ? &dsm : NULL, &dsp);
       }
       double wr = R->fw[r] * half;
       double Fn[3], Qn[3] = {0, 0, 0}, Gn[2][2];
@@ -866,7 +872,7 @@ void or_destroy(void* h) {
   if (!D) return;
   or_mesh* M = &D->mesh;
   free(M->nbr); free(M->nbr_face); free(M->detJ); free(M->dxi); free(M->normal);
-  free(M->flen); free(M->xq); free(M->vx); free(D->bed); free(D);
+  free(M->flen); free(M->xq); free(M->vx); free(M->fbc); free(D->bed); free(D);
 }
 
 int or_sizes(void* h, int* out) {
@@ -1367,6 +1373,20 @@ int or_bed_interpolate(void* h, const or_bed* bed, double* H) {
   return 0;
 }
 
+/* Boundary codes per local face ([n_el*nfc], kind | tag << 2, Sec. 5.2);
+ * interior faces are ignored; NULL: every boundary face takes the
+ * parameters' bc. */
+int or_set_boundary(void* h, const int8_t* codes) {
+  or_disc* D = h; or_mesh* M = &D->mesh;
+  size_t n = (size_t)M->n_el * D->ref.nfc;
+  for (size_t k = 0; k < n; ++k) {
+    int c = codes ? codes[k] : 0;
+    if (c < 0 || c > 15) return -1;
+    M->fbc[k] = (int8_t)(M->nbr[k] >= 0 ? 0 : c);
+  }
+  return 0;
+}
+
 /* Orders m1, m2, m3 of h, u and E (Sec. 5), each 0..P; P is the storage order. */
 int or_set_orders(void* h, int m1, int m2, int m3) {
   or_disc* D = h;
@@ -1512,7 +1532,7 @@ int or_point_psi(const or_params* p, double s, double* out) {
 int or_point_wall(const or_params* p, int dim, const double* n, const double* Xin, double* Xout) {
   pstate a, b;
   unpack(dim, Xin, &a);
-  bc_exterior(p, dim, n, &a, &b, NULL, NULL);
+  bc_exterior(p, dim, n, 0, &a, &b, NULL, NULL);
   Xout[0] = b.h;
   for (int k = 0; k < dim; ++k) Xout[1 + k] = b.u[k];
   for (int bb = 0; bb < dim; ++bb) for (int aa = 0; aa < dim; ++aa) Xout[1 + dim + bb * dim + aa] = b.E[aa][bb];
