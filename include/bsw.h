@@ -63,9 +63,11 @@ typedef struct bsw_disc_s* bsw_disc;
 
 /* Physical and regularisation parameters (Sec. 3: g, rho, alpha; Sec. 4: eta,
  * sigma0, gamma, beta and the regularisation k = reg in {1, 2, 3}).
- * bc applies to every boundary face: wall (mirror state: h+ = h-, u+ = R u-,
+ * bc applies to every boundary face without a code of its own
+ * (bsw_mesh_set_boundary): wall (mirror state: h+ = h-, u+ = R u-,
  * E+ = R E- R with R = I - 2 n n^T), homogeneous Neumann (V+ = V-, E+ = E-,
- * Sec. 5.2) or Dirichlet (exterior state = dirichlet[0..n_f-1], Sec. 5.2).
+ * Sec. 5.2) or Dirichlet (exterior state = dirichlet[0..n_f-1], Sec. 5.2;
+ * faces with tag t = 1..3 take dirichlet_tag[t-1] instead).
  * Regularisations 1 and 2 need sigma0 = 0 or sigma0 >= 1 / (2 beta). */
 typedef struct {
   double g, rho, alpha, eta, sigma0, gamma, beta;
@@ -75,6 +77,7 @@ typedef struct {
   int32_t jac_frozen;  /* Jacobian only: 0 exact (the HLL wave speeds S_L, S_R
                           differentiated), 1 the paper's Appendix A form with
                           S_L, S_R held fixed.  The residual is the same. */
+  double dirichlet_tag[3][7]; /* exterior states of Dirichlet faces tagged 1..3 */
 } bsw_params;
 
 /* Analytic initial condition, L2-projected with the element rule; E = 0.
@@ -167,6 +170,18 @@ const char* bsw_last_error(bsw_ctx ctx);
 int bsw_mesh_upload(bsw_ctx ctx, int dim, int64_t n_vert, const double* xy, int64_t n_el,
                     const int32_t* el2vert, bsw_mesh* out);
 int bsw_mesh_destroy(bsw_mesh mesh);
+/* Boundary condition of each boundary face (Sec. 5.2; the examples of
+ * Sec. 6.1 and 6.2 mix Dirichlet data of two depths, or a Neumann and a
+ * no-flow end).  face_bc (host, n_el * faces per element, index
+ * e * faces + local face; 1-D: face 0 at the element's first vertex, face 1
+ * at its second; triangles: face f from vertex f to f+1) holds
+ * code = kind | tag << 2: kind BSW_BC_WALL, BSW_BC_NEUMANN or
+ * BSW_BC_DIRICHLET, or 0 for the parameters' bc; a Dirichlet face takes the
+ * state of its tag (0: params.dirichlet, 1..3: params.dirichlet_tag[tag-1]).
+ * Interior faces' entries are ignored; NULL gives every boundary face code 0.
+ * The codes apply to every discretisation of the mesh; BSW_E_ARG for codes
+ * outside 0..15. */
+int bsw_mesh_set_boundary(bsw_mesh mesh, const int8_t* face_bc);
 
 /* ---------------------------------------------------------------- discretisation */
 /* Order P (1-D: 0..4; triangles: 1..3 with 3/7/12-point volume rules and P+1
@@ -335,6 +350,7 @@ typedef struct {
   bsw_bed bed;
   int32_t mixed_orders;    /* nonzero: the orders below apply (bsw_disc_set_orders) */
   int32_t m1, m2, m3;
+  const int8_t* face_bc;   /* optional per-face boundary codes (bsw_mesh_set_boundary) */
 } bsw_solve_request;
 
 /* Device bytes a request occupies while resident: state and 11 + gmres_m

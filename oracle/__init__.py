@@ -303,9 +303,9 @@ class Oracle:
         lib().or_jac_apply(self.h, C.byref(p), float(dt), _dp(We), _dp(xe), _dp(y))
         return from_elem(y)
 
-    def jac_blocks(self, params, W, dt, bc=1):
+    def jac_blocks(self, params, W, dt, bc=1, dirichlet=None):
         """Diagonal blocks, [n_el, bs, bs] with row/col index f*N_p + i."""
-        p = self._mp(params, bc)
+        p = self._mp(params, bc, dirichlet)
         We = to_elem(W); bs = self.nf * self.np
         B = np.zeros((self.n_el, bs, bs))
         lib().or_jac_blocks(self.h, C.byref(p), float(dt), _dp(We), _dp(B))

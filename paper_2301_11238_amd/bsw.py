@@ -28,7 +28,7 @@ class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("rho", C.c_double), ("alpha", C.c_double), ("eta", C.c_double),
                 ("sigma0", C.c_double), ("gamma", C.c_double), ("beta", C.c_double),
                 ("reg", C.c_int32), ("bc", C.c_int32), ("dirichlet", C.c_double * 7),
-                ("jac_frozen", C.c_int32)]
+                ("jac_frozen", C.c_int32), ("dirichlet_tag", (C.c_double * 7) * 3)]
 
 
 class IC(C.Structure):
@@ -66,7 +66,8 @@ class SolveRequest(C.Structure):
     _fields_ = [("n_vert", C.c_int64), ("xy", C.POINTER(C.c_double)), ("n_el", C.c_int64),
                 ("el2vert", C.POINTER(C.c_int32)), ("P", C.c_int32), ("precision", C.c_int32),
                 ("params", Params), ("ic", IC), ("W0", C.c_void_p), ("opts", SolveOpts), ("bed", Bed),
-                ("mixed_orders", C.c_int32), ("m1", C.c_int32), ("m2", C.c_int32), ("m3", C.c_int32)]
+                ("mixed_orders", C.c_int32), ("m1", C.c_int32), ("m2", C.c_int32), ("m3", C.c_int32),
+                ("face_bc", C.POINTER(C.c_int8))]
 
 
 BSW_REQ_QUEUED, BSW_REQ_RUNNING, BSW_REQ_DONE, BSW_REQ_FAILED, BSW_REQ_CANCELLED = range(5)
@@ -80,6 +81,7 @@ SIGNATURES = {
     "bsw_last_error": (C.c_char_p, [_VP]),
     "bsw_mesh_upload": (C.c_int, [_VP, C.c_int, C.c_int64, _DP, C.c_int64, C.POINTER(C.c_int32), C.POINTER(_VP)]),
     "bsw_mesh_destroy": (C.c_int, [_VP]),
+    "bsw_mesh_set_boundary": (C.c_int, [_VP, C.POINTER(C.c_int8)]),
     "bsw_disc_create": (C.c_int, [_VP, C.c_int, C.c_int, C.POINTER(_VP)]),
     "bsw_disc_destroy": (C.c_int, [_VP]),
     "bsw_disc_info": (C.c_int, [_VP, _I64P]),
@@ -134,7 +136,7 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def make_params(p, bc: int = 1, dirichlet=None) -> Params:
+def make_params(p, bc: int = 1, dirichlet=None, dirichlet_tags=None) -> Params:
     q = Params()
     for k in ("g", "rho", "alpha", "eta", "sigma0", "gamma", "beta"):
         setattr(q, k, float(getattr(p, k)))
@@ -144,6 +146,9 @@ def make_params(p, bc: int = 1, dirichlet=None) -> Params:
     if dirichlet is not None:
         for i, v in enumerate(dirichlet):
             q.dirichlet[i] = float(v)
+    for t, st in enumerate(dirichlet_tags or []):
+        for i, v in enumerate(st):
+            q.dirichlet_tag[t][i] = float(v)
     return q
 
 
@@ -236,6 +241,17 @@ class Mesh:
         self.h = h
         self.dim = dim
         self.n_el = e2v.shape[0]
+
+    def set_boundary(self, face_bc=None):
+        """Per-face boundary codes [n_el, faces] (kind | tag << 2), or None."""
+        import numpy as np
+        if face_bc is None:
+            rc = lib().bsw_mesh_set_boundary(self.h, None)
+        else:
+            c = np.ascontiguousarray(face_bc, dtype=np.int8).reshape(-1)
+            assert c.size == self.n_el * (self.dim + 1)
+            rc = lib().bsw_mesh_set_boundary(self.h, c.ctypes.data_as(C.POINTER(C.c_int8)))
+        self.ctx._check(rc, self.ctx.h)
 
     def close(self):
         if getattr(self, "h", None):
@@ -373,7 +389,7 @@ class Disc:
 class _ReqArrays:
     """Keeps the host arrays of a request alive until it is submitted."""
 
-    def __init__(self, xy, el2vert, P, precision, params, ic, opts, W0=None, bed=None, orders=None):
+    def __init__(self, xy, el2vert, P, precision, params, ic, opts, W0=None, bed=None, orders=None, face_bc=None):
         import numpy as np
         self.xy = np.ascontiguousarray(xy, dtype=np.float64)
         self.e2v = np.ascontiguousarray(el2vert, dtype=np.int32)
@@ -392,6 +408,10 @@ class _ReqArrays:
         r.W0 = C.c_void_p(self.W0.ctypes.data) if self.W0 is not None else None
         r.opts = opts.c()
         r.bed = make_bed(bed)
+        self.fbc = None
+        if face_bc is not None:
+            self.fbc = np.ascontiguousarray(face_bc, dtype=np.int8).reshape(-1)
+            r.face_bc = self.fbc.ctypes.data_as(C.POINTER(C.c_int8))
         if orders is not None:
             r.mixed_orders = 1
             r.m1, r.m2, r.m3 = (int(m) for m in orders)
@@ -452,9 +472,9 @@ class Server:
             pass
 
     def submit(self, xy, el2vert, P: int, precision: int, params: Params, ic=None, opts: Options = None,
-               W0=None, bed=None, orders=None) -> int:
+               W0=None, bed=None, orders=None, face_bc=None) -> int:
         opts = opts or Options()
-        a = _ReqArrays(xy, el2vert, P, precision, params, ic, opts, W0, bed, orders)
+        a = _ReqArrays(xy, el2vert, P, precision, params, ic, opts, W0, bed, orders, face_bc)
         t = C.c_uint64(0)
         self.ctx._check(lib().bsw_solve_submit(self.h, C.byref(a.req), C.byref(t)), self.ctx.h)
         n_p = (P + 1) * (P + 2) // 2

@@ -208,6 +208,8 @@ struct BatchEngine {
   double* sch = nullptr;          // pinned, device-mapped mirror of sc
   double* sch_dev = nullptr;
   double* ystage = nullptr;       // pinned staging of Krylov combination weights
+  T* d_dirtab = nullptr;          // device [kMaxBatch][28]: Dirichlet states of boundary tags 0..3
+  T* h_dirtab = nullptr;          // pinned staging of d_dirtab
   std::atomic<int64_t> ticks{0}, launches{0};
 
   ~BatchEngine() {
@@ -218,6 +220,8 @@ struct BatchEngine {
     if (h_desc) (void)hipHostFree(h_desc);
     if (sch) (void)hipHostFree(sch);
     if (ystage) (void)hipHostFree(ystage);
+    hfree(d_dirtab);
+    if (h_dirtab) (void)hipHostFree(h_dirtab);
   }
 
   int init(bsw_ctx ctx, int dim_, int P_, int M_) {
@@ -237,6 +241,9 @@ struct BatchEngine {
     HIPCHK(c, hipHostMalloc((void**)&sch, sizeof(double) * kMaxBatch * kScStride, hipHostMallocMapped));
     HIPCHK(c, hipHostGetDevicePointer((void**)&sch_dev, sch, 0));
     HIPCHK(c, hipHostMalloc((void**)&ystage, sizeof(double) * kMaxBatch * 72, hipHostMallocDefault));
+    if (int rc = dev_alloc(c, &d_dirtab, (size_t)kMaxBatch * 28)) return rc;
+    HIPCHK(c, hipHostMalloc((void**)&h_dirtab, sizeof(T) * kMaxBatch * 28, hipHostMallocDefault));
+    std::memset(h_dirtab, 0, sizeof(T) * kMaxBatch * 28);
     std::memset(h_desc, 0, sizeof(InstDesc<T>) * kMaxBatch);
     return BSW_OK;
   }
@@ -489,7 +496,10 @@ struct BatchEngine {
     d.m = view<T>(I->disc);
     bsw_params pc = I->prm;
     if (I->gamma_cur > 0) pc.gamma = I->gamma_cur;
-    d.p = devparams<T>(pc, I->dtk > 0 ? I->dtk : I->dt);
+    double v[28];
+    dirichlet_table(pc, v);
+    for (int i = 0; i < 28; ++i) h_dirtab[(size_t)k * 28 + i] = (T)v[i];
+    d.p = devparams<T>(pc, I->dtk > 0 ? I->dtk : I->dt, d_dirtab + (size_t)k * 28);
     d.ws = I->ws;
     d.ld = I->ld;
     d.len = I->len;
@@ -506,6 +516,7 @@ struct BatchEngine {
   // the pinned staging is only rewritten after a stream synchronisation
   int upload_desc() {
     HIPCHK(c, hipMemcpyAsync(d_desc, h_desc, sizeof(InstDesc<T>) * kMaxBatch, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d_dirtab, h_dirtab, sizeof(T) * kMaxBatch * 28, hipMemcpyHostToDevice, c->stream));
     return BSW_OK;
   }
 
@@ -1072,6 +1083,7 @@ struct Request {
   bsw_ic ic{};
   bsw_bed bed{};
   int orders[3] = {-1, -1, -1};  // m1, m2, m3 (-1: the uniform order P)
+  std::vector<int8_t> face_bc;    // per-face boundary codes (empty: the parameters' bc)
   bsw_solve_opts opt{};
   std::vector<unsigned char> W;   // result (host copy)
   bsw_solve_stats st{};
@@ -1103,6 +1115,7 @@ struct EngineImpl final : EngineIf {
     I->prm = r->prm;
     I->opt = r->opt;
     int rc = bsw_mesh_upload(c, 2, r->n_vert, r->xy.data(), r->n_el, r->e2v.data(), &I->mesh);
+    if (!rc && !r->face_bc.empty()) rc = bsw_mesh_set_boundary(I->mesh, r->face_bc.data());
     if (!rc) rc = bsw_disc_create(I->mesh, r->P, r->precision, &I->disc);
     if (!rc) rc = check_params(I->disc, &I->prm);
     if (!rc && r->orders[0] >= 0) rc = bsw_disc_set_orders(I->disc, r->orders[0], r->orders[1], r->orders[2]);
@@ -1343,6 +1356,9 @@ int check_request(bsw_ctx c, const bsw_solve_request* q) {
   if (b.kind < BSW_BED_FLAT || b.kind > BSW_BED_GAUSS || (b.kind != BSW_BED_FLAT && (b.order < 0 || b.order > q->P)) ||
       (b.kind == BSW_BED_GAUSS && !(b.d > 0)))
     return fail(c, BSW_E_ARG, "bad bed (kind, order 0..P, GAUSS d > 0)");
+  if (q->face_bc)
+    for (int64_t k = 0; k < 3 * q->n_el; ++k)
+      if (q->face_bc[k] < 0 || q->face_bc[k] > 15) return fail(c, BSW_E_ARG, "boundary codes must be in 0..15");
   if (q->mixed_orders) {
     const int m[3] = {q->m1, q->m2, q->m3};
     for (int k = 0; k < 3; ++k)
@@ -1447,6 +1463,7 @@ int bsw_solve_submit(bsw_server S, const bsw_solve_request* q, uint64_t* ticket)
   r->prm = q->params;
   r->ic = q->ic;
   r->bed = q->bed;
+  if (q->face_bc) r->face_bc.assign(q->face_bc, q->face_bc + 3 * q->n_el);
   if (q->mixed_orders) {
     r->orders[0] = q->m1;
     r->orders[1] = q->m2;

@@ -62,7 +62,7 @@ template <class T>
 struct DevParams {
   T g, gc, gs, rho_inv, eta, s0, gam, bet, inv_dt;
   int reg, bc, jfrozen;
-  T dir[7];
+  const T* dirtab;  // device [4][7]: Dirichlet exterior states of boundary tags 0..3
 };
 
 template <class T>
@@ -72,7 +72,8 @@ struct MeshView {
   const T* detJ;     // [n_el]
   const T* nrm;      // [NFC*D][n_el]
   const T* hlen;     // [NFC][n_el] : face length / 2 (2-D), 1 (1-D)
-  const int* nbr;    // [NFC][n_el] : 4*neighbour + neighbour's local face, -1 on the boundary
+  const int* nbr;    // [NFC][n_el] : 4*neighbour + neighbour's local face; on the boundary
+                     // -1 - code, code = kind | tag << 2 (kind 0: the parameters' bc)
   const double* vert;  // [(D+1)*D][n_el] vertex coordinates (FP64)
   const T* bed;        // [NP][n_el] modal coefficients of the bed H; nullptr = flat bed
   int nmodes;          // modes used by h | u << 8 | E << 16 (orders m1, m2, m3; NP when uniform)
@@ -245,17 +246,27 @@ __device__ __forceinline__ void mirror(const T* n, const Pt<D, T>& in, Pt<D, T>&
     }
 }
 
-// exterior state; for the tangent, din -> dout (Dirichlet: zero)
+// Exterior state of a boundary face with code = kind | tag << 2 (Sec. 5.2):
+// kind 1 wall, 2 Neumann, 3 Dirichlet, 0 the parameters' bc; a Dirichlet face
+// reads its tag's state from a small device table when it needs it (kept out
+// of the kernel's uniform registers).  For the tangent, din -> dout
+// (Dirichlet: zero).
 template <int D, class T>
-__device__ __forceinline__ void exterior(const DevParams<T>& p, const T* n, const Pt<D, T>& in, Pt<D, T>& out) {
-  if (p.bc == 1) mirror<D, T>(n, in, out);
-  else if (p.bc == 2) out = in;
-  else unpack<D, T>(p.dir, out);
+__device__ __forceinline__ void exterior(const DevParams<T>& p, const T* n, int code, const Pt<D, T>& in,
+                                         Pt<D, T>& out) {
+  const int kind = (code & 3) ? (code & 3) : p.bc;
+  if (kind == 1) mirror<D, T>(n, in, out);
+  else if (kind == 2) out = in;
+  else {
+    unpack<D, T>(p.dirtab + 7 * (code >> 2), out);
+  }
 }
 template <int D, class T>
-__device__ __forceinline__ void exterior_tan(const DevParams<T>& p, const T* n, const Pt<D, T>& din, Pt<D, T>& dout) {
-  if (p.bc == 1) mirror<D, T>(n, din, dout);
-  else if (p.bc == 2) dout = din;
+__device__ __forceinline__ void exterior_tan(const DevParams<T>& p, const T* n, int code, const Pt<D, T>& din,
+                                             Pt<D, T>& dout) {
+  const int kind = (code & 3) ? (code & 3) : p.bc;
+  if (kind == 1) mirror<D, T>(n, din, dout);
+  else if (kind == 2) dout = din;
   else {
     dout.h = T(0);
 #pragma unroll

@@ -503,8 +503,8 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
             unpack<D, T>(dXp, dsp);
           }
         } else {
-          exterior<D, T>(p, nv, sm, sp);
-          if constexpr (TAN) exterior_tan<D, T>(p, nv, dsm, dsp);
+          exterior<D, T>(p, nv, -1 - code, sm, sp);
+          if constexpr (TAN) exterior_tan<D, T>(p, nv, -1 - code, dsm, dsp);
         }
         T FV[1 + D], FE[D * D];
         if constexpr (TAN) face_flux_tan<D, T>(p, nv, wr, sm, sp, dsm, dsp, FV, FE);
@@ -642,8 +642,8 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
           unpack<D, T>(dXp, dsp);
         }
       } else {
-        exterior<D, T>(p, nv, sm, sp);
-        exterior_tan<D, T>(p, nv, dsm, dsp);
+        exterior<D, T>(p, nv, -1 - code, sm, sp);
+        exterior_tan<D, T>(p, nv, -1 - code, dsm, dsp);
       }
       T FV[1 + D], FE[D * D];
       face_flux_tan<D, T>(p, nv, tb.fw[rr] * hl, sm, sp, dsm, dsp, FV, FE);

@@ -49,6 +49,7 @@ struct bsw_mesh_s {
   DevMesh<double> m64;
   DevMesh<float> m32;
   std::vector<double> h_dxi, h_detJ, h_nrm, h_hlen;  // host copies for the FP32 view
+  std::vector<int> h_nbr;                            // host copy of the face map (boundary: -1)
 };
 
 struct bsw_disc_s {
@@ -58,6 +59,9 @@ struct bsw_disc_s {
   int bs = 0;
   size_t wsize = 0;  // bytes per real
   const void* bed = nullptr;   // bed coefficients [n_p][n_el] (caller's device memory), nullptr = flat
+  void* dirtab = nullptr;      // device [4][7]: Dirichlet states of boundary tags 0..3
+  double dirtab_host[28] = {}; // the values last written there
+  bool dirtab_set = false;
   int nmode[3] = {0, 0, 0};    // modes used by h, u and E (orders m1, m2, m3)
   // linearisation
   const void* lin_W = nullptr;
@@ -160,7 +164,7 @@ MeshView<T> view(bsw_disc d) {
 }
 
 template <class T>
-DevParams<T> devparams(const bsw_params& p, double dt) {
+DevParams<T> devparams(const bsw_params& p, double dt, const T* dirtab) {
   DevParams<T> q;
   q.g = (T)p.g;
   q.gc = (T)(p.g * std::cos(p.alpha));
@@ -169,8 +173,32 @@ DevParams<T> devparams(const bsw_params& p, double dt) {
   q.eta = (T)p.eta; q.s0 = (T)p.sigma0; q.gam = (T)p.gamma; q.bet = (T)p.beta;
   q.inv_dt = dt > 0 ? (T)(1.0 / dt) : T(0);
   q.reg = p.reg; q.bc = p.bc; q.jfrozen = p.jac_frozen != 0;
-  for (int k = 0; k < 7; ++k) q.dir[k] = (T)p.dirichlet[k];
+  q.dirtab = dirtab;
   return q;
+}
+
+// the Dirichlet states of p (tags 0..3) in the discretisation's device table,
+// rewritten only when they change (after the stream has drained, so kernels
+// already queued keep the values they were launched with)
+void dirichlet_table(const bsw_params& p, double* v) {
+  for (int k = 0; k < 7; ++k) v[k] = p.dirichlet[k];
+  for (int t = 0; t < 3; ++t)
+    for (int k = 0; k < 7; ++k) v[7 * (t + 1) + k] = p.dirichlet_tag[t][k];
+}
+
+template <class T>
+int sync_dirtab(bsw_disc d, const bsw_params& p) {
+  double v[28];
+  dirichlet_table(p, v);
+  if (d->dirtab_set && std::memcmp(v, d->dirtab_host, sizeof(v)) == 0) return BSW_OK;
+  bsw_ctx c = d->mesh->ctx;
+  T tv[28];
+  for (int k = 0; k < 28; ++k) tv[k] = (T)v[k];
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(d->dirtab, tv, sizeof(tv), hipMemcpyHostToDevice));
+  std::memcpy(d->dirtab_host, v, sizeof(v));
+  d->dirtab_set = true;
+  return BSW_OK;
 }
 
 int check_params(bsw_disc d, const bsw_params* p) {
@@ -532,11 +560,12 @@ struct OpLaunch {
   int operator()() {
     auto m = view<T>(d);
     hipStream_t st = d->mesh->ctx->stream;
+    if (int rc = sync_dirtab<T>(d, *p)) return rc;
     hipLaunchKernelGGL((k_trace<D, P, T>), grid1((int64_t)Shape<D, P>::NF * Shape<D, P>::NFC * m.n_el), dim3(256), 0,
                        st, (const T*)W, (T*)d->trA, m.n_el);
     hipLaunchKernelGGL((k_elem_blocked<D, P, T, 0>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0, st, (const T*)W,
                        (const T*)nullptr, (const T*)bold, (T*)R, (const T*)d->trA, (const T*)nullptr, m,
-                       devparams<T>(*p, dt));
+                       devparams<T>(*p, dt, (const T*)d->dirtab));
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -548,7 +577,7 @@ struct StepBeginLaunch {
   int operator()() {
     auto m = view<T>(d);
     hipLaunchKernelGGL((k_step_begin<D, P, T>), grid1(m.n_el), dim3(256), 0, d->mesh->ctx->stream, (const T*)W,
-                       (T*)bold, m, devparams<T>(*p, dt));
+                       (T*)bold, m, devparams<T>(*p, dt, (const T*)nullptr));
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -566,7 +595,8 @@ struct JacApplyLaunch {
     const dim3 gt = grid1((int64_t)Shape<D, P>::NF * Shape<D, P>::NFC * m.n_el), ge = grid1(m.n_el, Blk<D, P>::EB);
     const T* tL = (const T*)d->trL;
     T* tX = (T*)d->trX;
-    const auto prm = devparams<T>(d->lin_prm, d->lin_dt);
+    if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
+    const auto prm = devparams<T>(d->lin_prm, d->lin_dt, (const T*)d->dirtab);
     if (ev_start) {
       hipExtLaunchKernelGGL((k_trace<D, P, T>), gt, dim3(256), 0, st, ev_start, nullptr, 0, (const T*)x, tX, m.n_el);
       hipExtLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), ge, dim3(256), 0, st, nullptr, ev_stop, 0,
@@ -589,10 +619,12 @@ struct LinearizeLaunch {
     auto m = view<T>(d);
     bsw_ctx c = d->mesh->ctx;
     const int tpb = S::BS <= 64 ? 64 : 128;
+    if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
     hipLaunchKernelGGL((k_trace<D, P, T>), grid1((int64_t)S::NF * S::NFC * m.n_el), dim3(256), 0, c->stream,
                        (const T*)d->lin_W, (T*)d->trL, m.n_el);
     hipLaunchKernelGGL((k_jac_columns<D, P, T>), dim3(m.n_el), dim3(tpb), 0, c->stream, (const T*)d->lin_W,
-                       (const T*)d->trL, (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt));
+                       (const T*)d->trL, (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt,
+                                                                            (const T*)d->dirtab));
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL((k_block_inverse<S::BS, T>), dim3(m.n_el), dim3(inv_threads<S::BS>()), 0, c->stream,
                        (const T*)d->blocks_raw, (float*)d->blocks, m.n_el);
@@ -860,7 +892,26 @@ int bsw_mesh_upload(bsw_ctx c, int dim, int64_t n_vert, const double* xy, int64_
   if (!rc) rc = up(&M->m64.hlen, hlen);
   if (rc) { bsw_mesh_destroy(M); return rc; }
   M->h_dxi = std::move(dxi); M->h_detJ = std::move(detJ); M->h_nrm = std::move(nrm); M->h_hlen = std::move(hlen);
+  M->h_nbr = std::move(nbr);
   *out = M;
+  return BSW_OK;
+}
+
+int bsw_mesh_set_boundary(bsw_mesh M, const int8_t* face_bc) {
+  if (!M) return fail(nullptr, BSW_E_ARG, "null mesh");
+  bsw_ctx c = M->ctx;
+  const int64_t n = M->n_el;
+  const int nfc = M->nfc;
+  std::vector<int> nbr(M->h_nbr);
+  for (int64_t e = 0; e < n; ++e)
+    for (int f = 0; f < nfc; ++f) {
+      const int code = face_bc ? (int)face_bc[e * nfc + f] : 0;
+      if (code < 0 || code > 15) return fail(c, BSW_E_ARG, "boundary codes must be in 0..15");
+      int& v = nbr[(size_t)f * n + e];
+      if (v < 0) v = -1 - code;
+    }
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipMemcpy(M->nbr, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice));
   return BSW_OK;
 }
 
@@ -911,6 +962,7 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
     if (!rc && hipMalloc(t, ntr) != hipSuccess) rc = fail(c, BSW_E_OOM, "face-trace storage");
   if (!rc) rc = dev_alloc(c, &d->red_out, 64);
   if (!rc) rc = dev_alloc(c, &d->hcoef, 80);
+  if (!rc && hipMalloc(&d->dirtab, 28 * d->wsize) != hipSuccess) rc = fail(c, BSW_E_OOM, "Dirichlet table");
   if (!rc && hipHostMalloc((void**)&d->red_host, 80 * sizeof(double), hipHostMallocMapped) != hipSuccess)
     rc = fail(c, BSW_E_OOM, "hipHostMalloc");
   if (!rc && hipHostGetDevicePointer((void**)&d->red_dev_map, d->red_host, 0) != hipSuccess)
@@ -925,7 +977,7 @@ int bsw_disc_destroy(bsw_disc d) {
   hfree(d->blocks); hfree(d->blocks_raw); hfree(d->part); hfree(d->red_out);
   hfree(d->trL); hfree(d->trA); hfree(d->trX);
   if (d->eng) d->eng_free(d->eng);
-  hfree(d->gm); hfree(d->hcoef);
+  hfree(d->gm); hfree(d->hcoef); hfree(d->dirtab);
   if (d->red_host) (void)hipHostFree(d->red_host);
   delete d;
   return BSW_OK;
