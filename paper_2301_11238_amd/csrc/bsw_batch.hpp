@@ -443,7 +443,7 @@ struct BatchEngine {
   // fold the partials of rows[] rows per instance into sc / sch at offset off
   // (scl, sig: as kb_rows_final; jv: per-instance Krylov index)
   int final_rows(const std::vector<int>& L, const std::vector<int>& rows, int etile, unsigned ops, int off,
-                 int scl = 0, int sig = -1, const std::vector<int>* jv = nullptr) {
+                 int scl = 0, int sig = -1, const std::vector<int>* jv = nullptr, int gate = -1) {
     BatchSet S;
     build(S, L, K_ONE, jv);
     int mr = 0;
@@ -453,7 +453,7 @@ struct BatchEngine {
     }
     if (!mr) return BSW_OK;
     hipLaunchKernelGGL((kb_rows_final<T>), dim3((unsigned)L.size(), mr), dim3(256), 0, c->stream, d_desc, S, etile,
-                       ops, sc, sch_dev, off, scl, sig);
+                       ops, sc, sch_dev, off, scl, sig, gate);
     HIPCHK(c, hipGetLastError());
     ++launches;
     return BSW_OK;
@@ -590,12 +590,14 @@ struct BatchEngine {
   }
 
   // ------------------------------------------------------------ GMRES (lockstep, pipelined)
-  // Right-preconditioned restarted GMRES(M) with classical Gram-Schmidt done
-  // twice, per instance: J x = rhs to ||rhs - J x|| <= rtol ||rhs|| with
-  // x = B_DW starting at 0.  One Arnoldi step of every participating instance
-  // is nine launches (preconditioner, traces, Jacobian, dots, fused
-  // subtraction and dots, new vector and its norm, and a fold kernel after
-  // each of the three reductions); the
+  // Right-preconditioned restarted GMRES(M) with classical Gram-Schmidt and a
+  // second pass where the first cancelled more than half of the squared norm
+  // (gs_refine, decided on the device per instance), per instance:
+  // J x = rhs to ||rhs - J x|| <= rtol ||rhs|| with x = B_DW starting at 0.
+  // One Arnoldi step of every participating instance is nine launches
+  // (preconditioner, traces, Jacobian, dots with ||w||^2, the second pass
+  // (an immediate return where it is not needed), new vector and its norm,
+  // and a fold kernel after each of the three reductions); the
   // Hessenberg column, Givens rotations and the cycle test run on the host
   // from the mapped scalars.  The host issues step t+1 before it reads step
   // t (Krylov index and iteration cap known in advance), so the device never
@@ -657,14 +659,15 @@ struct BatchEngine {
     if (int rc = dispatchT<T>(dim, P, fj)) return rc;
     if (int rc = elem_pass(1, L, jv, (int)B_W, (int)B_Z, (int)B_WK, timing ? jt1[pa] : nullptr)) return rc;
     --launches;  // counted in the tick's nine
-    // pass 1: h1 = V^T w
+    // pass 1: h1 = V^T w and w . w
     nt = build(S, L, K_VEC, jv);
     hipLaunchKernelGGL((kb_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
     std::vector<int> rows(L.size());
-    for (size_t a = 0; a < L.size(); ++a) rows[a] = tk.jv[a] + 1;
+    for (size_t a = 0; a < L.size(); ++a) rows[a] = tk.jv[a] + 2;
     if (int rc = final_rows(L, rows, 0, 0u, offA, 1, -1, jv)) return rc;
-    // pass 2: w -= V h1; h2 = V^T w, w . w
+    // pass 2 where the first left less than half of w's squared norm (the
+    // device decides per instance): h2 = V^T (w - V h1); else h2 = 0
     int maxrows = 0;
     for (int j : tk.jv) maxrows = std::max(maxrows, j + 1);
     if (maxrows <= kRowsCached)
@@ -674,11 +677,11 @@ struct BatchEngine {
       hipLaunchKernelGGL((kb_axpy_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
                          (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
-    for (auto& r : rows) r += 1;
-    if (int rc = final_rows(L, rows, 0, 0u, offB, 1, -1, jv)) return rc;
-    // V_{j+1} = w - V h2 and its norm (sigma_{j+1} = 1 / norm)
-    hipLaunchKernelGGL((kb_normalize<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offB,
-                       (int)B_V0, (int)B_WK);
+    for (auto& r : rows) r -= 1;
+    if (int rc = final_rows(L, rows, 0, 0u, offB, 1, -1, jv, offA)) return rc;
+    // V_{j+1} = w - V (h1 + h2) and its norm (sigma_{j+1} = 1 / norm)
+    hipLaunchKernelGGL((kb_normalize<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
+                       offB, (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
     std::fill(rows.begin(), rows.end(), 1);
     if (int rc = final_rows(L, rows, 0, 0u, kScN + pa, 0, 1, jv)) return rc;

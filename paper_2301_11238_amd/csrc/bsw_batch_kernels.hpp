@@ -268,7 +268,20 @@ __device__ __forceinline__ void tile_dots(const InstDesc<T>& I, const T* __restr
   }
 }
 
-// Gram-Schmidt pass 1: partials of V_r . w, r <= j
+// Classical Gram-Schmidt with the "refine if needed" test of Daniel, Gragg,
+// Kaufman and Stewart (1976): the second pass is taken only when the first
+// removed more than half of the squared norm, ||w - Q h||^2 = ||w||^2 -
+// ||h||^2 < ||w||^2 / 2 (Q the normalised basis).  s holds h_0..h_{rows-1}
+// (coefficients against Q) and ||w||^2; every kernel that needs the decision
+// evaluates it from the same values in the same order.
+__device__ __forceinline__ bool gs_refine(const double* __restrict__ s, int rows) {
+  double hh = 0.0;
+  for (int r = 0; r < rows; ++r) hh += s[r] * s[r];
+  const double ww = s[rows];
+  return ww - hh < 0.5 * ww;
+}
+
+// Gram-Schmidt pass 1: partials of V_r . w (r <= j) and of w . w
 template <class T>
 __global__ void __launch_bounds__(256) kb_dots(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0, int sw) {
   const int ai = bset_find(A, blockIdx.x);
@@ -277,14 +290,15 @@ __global__ void __launch_bounds__(256) kb_dots(const InstDesc<T>* __restrict__ d
   const T* w = bslot(I, sw, 0);
   const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
   const double w0 = i0 < I.len ? (double)w[i0] : 0.0, w1 = i1 < I.len ? (double)w[i1] : 0.0;
-  tile_dots<T>(I, bslot(I, sV0, 0), w0, w1, i0, A.jv[ai] + 1, 0, t);
+  tile_dots<T>(I, bslot(I, sV0, 0), w0, w1, i0, A.jv[ai] + 2, 1, t);
 }
 
-// w <- w - sum_{r <= j} h_r sigma_r V_r (h in row coff), then the partials of
-// V_r . w (r <= j) and w . w: the subtraction of pass 1 and the dots of pass 2
-// The same with each lane's entries of V_0..V_j kept in registers between the
-// subtraction and the dots (one read of the basis instead of two); for
-// instances with j + 1 <= kRowsCached.
+// Gram-Schmidt pass 2, only where gs_refine asks for it (else the workgroup
+// returns at once and the fold writes zeros): t = w - sum_{r <= j} h_r
+// sigma_r V_r (h and ||w||^2 in row coff) in registers, w itself untouched,
+// then the partials of V_r . t (r <= j).  This variant keeps each lane's
+// entries of V_0..V_j in registers between the subtraction and the dots (one
+// read of the basis instead of two); for instances with j + 1 <= kRowsCached.
 constexpr int kRowsCached = 32;
 
 template <class T>
@@ -297,9 +311,10 @@ __global__ void __launch_bounds__(256) kb_axpy_dots_cached(const InstDesc<T>* __
   const int t = blockIdx.x - A.tile0[ai];
   const int rows = A.jv[ai] + 1;
   const double* h = sc + (int64_t)slot * kScStride + coff;
+  if (!gs_refine(h, rows)) return;
   const double* sg = sc + (int64_t)slot * kScStride + kScS;
   const T* V = bslot(I, sV0, 0);
-  T* w = bslot(I, sw, 0);
+  const T* w = bslot(I, sw, 0);
   const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
   const bool in0 = i0 < I.len, in1 = i1 < I.len;
   T v0[kRowsCached], v1[kRowsCached];
@@ -316,22 +331,19 @@ __global__ void __launch_bounds__(256) kb_axpy_dots_cached(const InstDesc<T>* __
     a0 -= c * (double)v0[r];
     a1 -= c * (double)v1[r];
   }
-  if (in0) w[i0] = (T)a0;
-  if (in1) w[i1] = (T)a1;
-  const double w0 = in0 ? (double)(T)a0 : 0.0, w1 = in1 ? (double)(T)a1 : 0.0;
-  // partials of V_r . w (r < rows) and w . w (row `rows`), as tile_dots
+  const double w0 = in0 ? a0 : 0.0, w1 = in1 ? a1 : 0.0;
+  // partials of V_r . t (r < rows), as tile_dots
   __shared__ double red[8][257];
   const int tid = threadIdx.x, ru = tid >> 5, rl = tid & 31;
-  const int nrow = rows + 1;
+  const int nrow = rows;
 #pragma unroll
-  for (int r0 = 0; r0 <= kRowsCached; r0 += 8) {
+  for (int r0 = 0; r0 < kRowsCached; r0 += 8) {
     if (r0 < nrow) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int r = r0 + u;
         double a = 0.0;
-        if (r < kRowsCached && r < rows) a = (double)v0[r < kRowsCached ? r : 0] * w0 + (double)v1[r < kRowsCached ? r : 0] * w1;
-        else if (r == rows) a = w0 * w0 + w1 * w1;
+        if (r < rows) a = (double)v0[r] * w0 + (double)v1[r] * w1;
         red[u][tid] = a;
       }
       __syncthreads();
@@ -355,9 +367,10 @@ __global__ void __launch_bounds__(256) kb_axpy_dots(const InstDesc<T>* __restric
   const int t = blockIdx.x - A.tile0[ai];
   const int rows = A.jv[ai] + 1;
   const double* h = sc + (int64_t)slot * kScStride + coff;
+  if (!gs_refine(h, rows)) return;
   const double* sg = sc + (int64_t)slot * kScStride + kScS;
   const T* V = bslot(I, sV0, 0);
-  T* w = bslot(I, sw, 0);
+  const T* w = bslot(I, sw, 0);
   const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
   double a0 = i0 < I.len ? (double)w[i0] : 0.0, a1 = i1 < I.len ? (double)w[i1] : 0.0;
   {
@@ -380,25 +393,25 @@ __global__ void __launch_bounds__(256) kb_axpy_dots(const InstDesc<T>* __restric
       }
     }
   }
-  if (i0 < I.len) w[i0] = (T)a0;
-  if (i1 < I.len) w[i1] = (T)a1;
-  // the dots use the stored (rounded) values
-  a0 = i0 < I.len ? (double)(T)a0 : 0.0;
-  a1 = i1 < I.len ? (double)(T)a1 : 0.0;
-  tile_dots<T>(I, V, a0, a1, i0, rows + 1, 1, t);
+  a0 = i0 < I.len ? a0 : 0.0;
+  a1 = i1 < I.len ? a1 : 0.0;
+  tile_dots<T>(I, V, a0, a1, i0, rows, 0, t);
 }
 
-// V_{j+1} <- w - sum_{r <= j} h_r sigma_r V_r (h in row coff), unnormalised,
-// and the partials of its squared norm
+// V_{j+1} <- w - sum_{r <= j} (h1_r + h2_r) sigma_r V_r (the two Gram-Schmidt
+// passes' coefficients, rows coff and coff2; h2 = 0 where the second pass was
+// skipped), unnormalised, and the partials of its squared norm
 template <class T>
 __global__ void __launch_bounds__(256) kb_normalize(const InstDesc<T>* __restrict__ ds, BatchSet A,
-                                                     const double* __restrict__ sc, int coff, int sV0, int sw) {
+                                                     const double* __restrict__ sc, int coff, int coff2, int sV0,
+                                                     int sw) {
   const int ai = bset_find(A, blockIdx.x);
   const int slot = A.inst[ai];
   const InstDesc<T> I = ds[slot];
   const int t = blockIdx.x - A.tile0[ai];
   const int rows = A.jv[ai] + 1;
   const double* h = sc + (int64_t)slot * kScStride + coff;
+  const double* h2 = sc + (int64_t)slot * kScStride + coff2;
   const double* sg = sc + (int64_t)slot * kScStride + kScS;
   const T* V = bslot(I, sV0, 0);
   const T* w = bslot(I, sw, 0);
@@ -414,7 +427,7 @@ __global__ void __launch_bounds__(256) kb_normalize(const InstDesc<T>* __restric
         const int r = r0 + u;
         const T* v = V + (int64_t)r * I.ld;
         const bool ok = r < rows;
-        c[u] = ok ? h[r] * sg[r] : 0.0;
+        c[u] = ok ? (h[r] + h2[r]) * sg[r] : 0.0;
         v0[u] = ok && in0 ? (double)v[i0] : 0.0;
         v1[u] = ok && in1 ? (double)v[i1] : 0.0;
       }
@@ -483,11 +496,13 @@ __global__ void __launch_bounds__(256) kb_vred(const InstDesc<T>* __restrict__ d
 // in a fixed order; op of row r is bits 2r..2r+1 of ops (0 sum, 1 max, 2 min)
 // scl: rows r <= j are multiplied by sigma_r (dots against stored Krylov
 // vectors); sig >= 0: row 0 is a sum of squares, its square root is written
-// and sigma_{j + sig} = 1 / root (0 for a zero vector)
+// and sigma_{j + sig} = 1 / root (0 for a zero vector); gate >= 0: rows of a
+// second Gram-Schmidt pass, zero where gs_refine on the first pass's row (at
+// gate) says the pass was skipped
 template <class T>
 __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restrict__ ds, BatchSet A, int etile,
                                                       unsigned ops, double* sc, double* sch, int off, int scl,
-                                                      int sig) {
+                                                      int sig, int gate) {
   const int ai = blockIdx.x;
   const int slot = A.inst[ai];
   const InstDesc<T> I = ds[slot];
@@ -495,8 +510,9 @@ __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restri
   if (r >= A.rows[ai]) return;
   const int op = r < 16 ? (int)((ops >> (2 * r)) & 3u) : 0;
   const int nt = etile ? I.ntile_e : I.ntile;
+  const bool skipped = gate >= 0 && !gs_refine(sc + (int64_t)slot * kScStride + gate, A.jv[ai] + 1);
   double acc = op == 0 ? 0.0 : (op == 1 ? -INFINITY : INFINITY);
-  for (int t = threadIdx.x; t < nt; t += 256) {
+  for (int t = threadIdx.x; t < (skipped ? 0 : nt); t += 256) {
     const double v = I.part[(int64_t)r * nt + t];
     acc = op == 0 ? acc + v : (op == 1 ? fmax(acc, v) : fmin(acc, v));
   }
