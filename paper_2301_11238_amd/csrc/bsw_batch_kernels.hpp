@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) kb_trace(const InstDesc<T>* __restrict__ 
 // with the traces of W in trL and of x in trX
 // NT: the element-tile shape (workgroup size), chosen by the autotuner
 template <int D, int P, class T, int MODE, int NT>
-__global__ void __launch_bounds__(NT) kb_elem(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW, int sX,
+__global__ void __launch_bounds__(NT, (elem_waves<D, P, T>())) kb_elem(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW, int sX,
                                                int sB, int sOut) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int ai = bset_find(A, b);

@@ -382,6 +382,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 constexpr int kTileShapes = 3;
 constexpr int kTileNT[kTileShapes] = {128, 256, 512};
 
+// Waves per SIMD the element pass is compiled for (register budget 512 / w):
+// 3 for the FP64 order-3 triangle (its point lanes need about 165 registers),
+// 4 otherwise.
+template <int D, int P, class T>
+constexpr int elem_waves() { return (D == 2 && P == 3 && sizeof(T) == 8) ? 3 : 4; }
+
 template <int D, int P, int NT = 256>
 struct Blk {
   using S = Shape<D, P>;
@@ -556,7 +562,7 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
 }
 
 template <int D, int P, class T, int MODE>
-__global__ void __launch_bounds__(256) k_elem_blocked(const T* __restrict__ W, const T* __restrict__ x,
+__global__ void __launch_bounds__(256, (elem_waves<D, P, T>())) k_elem_blocked(const T* __restrict__ W, const T* __restrict__ x,
                                                        const T* __restrict__ bold, T* __restrict__ out,
                                                        const T* __restrict__ trW, const T* __restrict__ trX,
                                                        MeshView<T> m, DevParams<T> p) {
