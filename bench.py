@@ -295,7 +295,7 @@ def main():
     op_bytes = bytes_per_element(2, problem.P, 8) * n_el
     jac_bytes = jac_bytes_per_element(2, problem.P, 8) * n_el
     bs = disc.nf * disc.np
-    pc_bytes = (8 * bs * bs + 4 * bs + 2 * 8 * bs) * n_el
+    pc_bytes = (4 * bs * bs + 2 * 8 * bs) * n_el   # FP32 inverse blocks, FP64 x read and y written
     kern = {
         "operator": dict(seconds=t_op, bytes=op_bytes),
         "jacobian_apply": dict(seconds=t_jac, bytes=jac_bytes),

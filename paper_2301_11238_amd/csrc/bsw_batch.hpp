@@ -266,7 +266,7 @@ struct BatchEngine {
       case K_ETILE: return (int)((I->n_el + eb_cur - 1) / eb_cur);
       case K_E256: return I->ntile_e;
       case K_E1: return (int)I->n_el;
-      case K_ITEM: return (int)((BS * I->n_el + 255) / 256);
+      case K_ITEM: return (int)(BS * ((I->n_el + 255) / 256));  // row tiles (row_tile)
       case K_VEC: return I->ntile;
       case K_TRACE: return (int)((NFNFC * I->n_el + 255) / 256);
     }

@@ -143,11 +143,13 @@ __global__ void __launch_bounds__(inv_threads<BS>()) kb_block_inverse(const Inst
 template <int BS, class T>
 __global__ void __launch_bounds__(256) kb_block_apply(const InstDesc<T>* __restrict__ ds, BatchSet A, int sX,
                                                        int sY) {
-  const int ai = bset_find(A, blockIdx.x);
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int ai = bset_find(A, b);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int j = A.jv[ai];
-  const int64_t idx = (int64_t)(blockIdx.x - A.tile0[ai]) * 256 + threadIdx.x;
-  if (idx < (int64_t)BS * I.m.n_el) block_apply_item<BS, T>(I.blk, bslot(I, sX, j), bslot(I, sY, j), I.m.n_el, idx);
+  int row, e;
+  row_tile<BS>(b - A.tile0[ai], row, e);
+  if (e < I.m.n_el) block_apply_item<BS, T>(I.blk, bslot(I, sX, j), bslot(I, sY, j), I.m.n_el, row, e);
 }
 
 // mass, active area, max wave speed, min depth per 256-element tile
@@ -449,15 +451,16 @@ __global__ void __launch_bounds__(256) kb_normalize(const InstDesc<T>* __restric
 template <int BS, class T>
 __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restrict__ ds, BatchSet A,
                                                        const double* __restrict__ sc, int sV0, int sZ) {
-  const int ai = bset_find(A, blockIdx.x);
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int ai = bset_find(A, b);
   const int slot = A.inst[ai];
   const InstDesc<T> I = ds[slot];
   const int j = A.jv[ai];
   const int n = I.m.n_el;
-  const int64_t idx = (int64_t)(blockIdx.x - A.tile0[ai]) * 256 + threadIdx.x;
-  if (idx >= (int64_t)BS * n) return;
+  int row, e;
+  row_tile<BS>(b - A.tile0[ai], row, e);
+  if (e >= n) return;
   const double sgm = sc[(int64_t)slot * kScStride + kScS + j];
-  const int row = (int)(idx / n), e = (int)(idx % n);
   const T* x = bslot(I, sV0, 0) + (int64_t)j * I.ld;
   const float* Ai = I.blk + (size_t)row * BS * n + e;
   double s = 0.0;

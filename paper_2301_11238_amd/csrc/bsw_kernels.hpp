@@ -791,10 +791,19 @@ __global__ void __launch_bounds__(inv_threads<BS>()) k_block_inverse(const T* __
 }
 
 // y = blockdiag(A_e)^{-1} x: one lane per (row, element), element fastest.
+// A launch tile is 256 elements of one row, and consecutive tiles take the
+// rows of the same elements (tile t: row t % BS, elements (t / BS) * 256 +
+// lane), so the BS rows of an element tile reuse its slice of x from the L2
+// of one XCD instead of refetching it from HBM for every row.
+template <int BS>
+__device__ __forceinline__ void row_tile(int t, int& row, int& e) {
+  row = t % BS;
+  e = (t / BS) * 256 + (int)threadIdx.x;
+}
+
 template <int BS, class T>
 __device__ __forceinline__ void block_apply_item(const float* __restrict__ Ainv, const T* __restrict__ x,
-                                                 T* __restrict__ y, int n, int64_t idx) {
-  const int row = (int)(idx / n), e = (int)(idx % n);
+                                                 T* __restrict__ y, int n, int row, int e) {
   const float* arow = Ainv + (size_t)row * BS * n + e;
   T s = T(0);
 #pragma unroll
@@ -805,8 +814,9 @@ __device__ __forceinline__ void block_apply_item(const float* __restrict__ Ainv,
 template <int BS, class T>
 __global__ void __launch_bounds__(256) k_block_apply(const float* __restrict__ Ainv, const T* __restrict__ x,
                                                       T* __restrict__ y, int n) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < (int64_t)BS * n) block_apply_item<BS, T>(Ainv, x, y, n, idx);
+  int row, e;
+  row_tile<BS>(xcd_tile(blockIdx.x, gridDim.x), row, e);
+  if (e < n) block_apply_item<BS, T>(Ainv, x, y, n, row, e);
 }
 
 // per-element contributions to the mass, the active (yielded) area, the

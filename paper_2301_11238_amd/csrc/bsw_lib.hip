@@ -639,7 +639,7 @@ struct PrecLaunch {
   int operator()() {
     using S = Shape<D, P>;
     auto m = view<T>(d);
-    hipLaunchKernelGGL((k_block_apply<S::BS, T>), grid1((int64_t)S::BS * m.n_el), dim3(256), 0,
+    hipLaunchKernelGGL((k_block_apply<S::BS, T>), dim3((unsigned)(S::BS * ((m.n_el + 255) / 256))), dim3(256), 0,
                        d->mesh->ctx->stream, (const float*)d->blocks, (const T*)x, (T*)y, m.n_el);
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
