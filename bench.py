@@ -286,7 +286,7 @@ def main():
     b = disc.step_begin(cp, dt, W)
     R = disc.empty()
     t_op = time_kernel(lambda: disc.operator_apply(cp, dt, W, b, R), stream)
-    disc.jacobian_linearize(cp, dt, W)
+    t_lin = time_kernel(lambda: disc.jacobian_linearize(cp, dt, W), stream, reps=5)
     x = torch.randn_like(W)
     y = disc.empty()
     t_jac = time_kernel(lambda: disc.jacobian_apply(x, y), stream)
@@ -300,6 +300,9 @@ def main():
         "operator": dict(seconds=t_op, bytes=op_bytes),
         "jacobian_apply": dict(seconds=t_jac, bytes=jac_bytes),
         "block_jacobi_solve": dict(seconds=t_pc, bytes=pc_bytes),
+        # linearisation: traces of W, the element Jacobian blocks (FP64,
+        # written then read by the inversion) and their FP32 inverses
+        "preconditioner_setup": dict(seconds=t_lin, bytes=(8 + 8 + 4) * bs * bs * n_el),
     }
     # the matrix-free Jacobian apply runs once per GMRES iteration: the dominant
     # kernel; its duration is the HIP-event average over the timed steps

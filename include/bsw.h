@@ -251,8 +251,8 @@ int bsw_operator_apply(bsw_disc disc, const bsw_params* prm, double dt, const vo
 /* ---------------------------------------------------------------- element-block Jacobian (Appendix A) */
 /* Records W (device pointer, kept by reference: the caller must not change or
  * free it until the next linearize), the parameters and dt; assembles the
- * diagonal blocks dR_e/dW_e of Eq. Newton and inverts them (LU with partial
- * pivoting) for the block-Jacobi preconditioner. */
+ * diagonal blocks dR_e/dW_e of Eq. Newton and inverts them (Gauss-Jordan with
+ * partial pivoting, inverses kept in FP32) for the block-Jacobi preconditioner. */
 int bsw_jacobian_linearize(bsw_disc disc, const bsw_params* prm, double dt, const void* W);
 /* y = (dR/dW)(W) x, the directional derivative including the face coupling to
  * neighbours (matrix-free): exact, HLL wave speeds included, or with them held

@@ -661,15 +661,18 @@ struct BatchEngine {
     --launches;  // counted in the tick's nine
     // pass 1: h1 = V^T w and w . w
     nt = build(S, L, K_VEC, jv);
-    hipLaunchKernelGGL((kb_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
+    int maxrows = 0;
+    for (int j : tk.jv) maxrows = std::max(maxrows, j + 1);
+    if (maxrows <= kRowsCached)
+      hipLaunchKernelGGL((kb_dots_cached<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
+    else
+      hipLaunchKernelGGL((kb_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
     std::vector<int> rows(L.size());
     for (size_t a = 0; a < L.size(); ++a) rows[a] = tk.jv[a] + 2;
     if (int rc = final_rows(L, rows, 0, 0u, offA, 1, -1, jv)) return rc;
     // pass 2 where the first left less than half of w's squared norm (the
     // device decides per instance): h2 = V^T (w - V h1); else h2 = 0
-    int maxrows = 0;
-    for (int j : tk.jv) maxrows = std::max(maxrows, j + 1);
     if (maxrows <= kRowsCached)
       hipLaunchKernelGGL((kb_axpy_dots_cached<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc,
                          offA, (int)B_V0, (int)B_WK);

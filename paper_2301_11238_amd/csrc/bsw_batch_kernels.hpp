@@ -134,10 +134,11 @@ __global__ void __launch_bounds__(128) kb_jac_columns(const InstDesc<T>* __restr
 }
 
 template <int BS, class T>
-__global__ void __launch_bounds__(inv_threads<BS>()) kb_block_inverse(const InstDesc<T>* __restrict__ ds, BatchSet A) {
-  const int ai = bset_find(A, blockIdx.x);
+__global__ void __launch_bounds__(inv_threads<BS>(), (inv_waves<BS, T>())) kb_block_inverse(const InstDesc<T>* __restrict__ ds, BatchSet A) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int ai = bset_find(A, b);
   const InstDesc<T> I = ds[A.inst[ai]];
-  block_inverse_elem<BS, T>(I.blk_raw, I.blk, I.m.n_el, blockIdx.x - A.tile0[ai]);
+  block_inverse_elem<BS, T>(I.blk_raw, I.blk, I.m.n_el, b - A.tile0[ai]);
 }
 
 template <int BS, class T>
@@ -295,13 +296,62 @@ __global__ void __launch_bounds__(256) kb_dots(const InstDesc<T>* __restrict__ d
   tile_dots<T>(I, bslot(I, sV0, 0), w0, w1, i0, A.jv[ai] + 2, 1, t);
 }
 
+// kb_dots for instances with j + 1 <= kRowsCached: every lane first loads its
+// entries of V_0..V_j (all loads in flight at once, not eight rows per round
+// trip), then the rows are reduced as in tile_dots, in the same order
+constexpr int kRowsCached = 32;
+
+template <class T>
+__global__ void __launch_bounds__(256) kb_dots_cached(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0,
+                                                       int sw) {
+  const int ai = bset_find(A, blockIdx.x);
+  const InstDesc<T> I = ds[A.inst[ai]];
+  const int t = blockIdx.x - A.tile0[ai];
+  const int nv = A.jv[ai] + 1, rows = nv + 1;  // the last row is w . w
+  const T* V = bslot(I, sV0, 0);
+  const T* w = bslot(I, sw, 0);
+  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
+  const bool in0 = i0 < I.len, in1 = i1 < I.len;
+  T v0[kRowsCached], v1[kRowsCached];
+#pragma unroll
+  for (int r = 0; r < kRowsCached; ++r) {
+    const T* v = V + (int64_t)r * I.ld;
+    v0[r] = r < nv && in0 ? v[i0] : T(0);
+    v1[r] = r < nv && in1 ? v[i1] : T(0);
+  }
+  const double w0 = in0 ? (double)w[i0] : 0.0, w1 = in1 ? (double)w[i1] : 0.0;
+  __shared__ double red[8][257];
+  const int tid = threadIdx.x, ru = tid >> 5, rl = tid & 31;
+#pragma unroll
+  for (int r0 = 0; r0 < kRowsCached + 8; r0 += 8) {
+    if (r0 < rows) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = r0 + u;
+        double a = 0.0;
+        if (r < kRowsCached && r < nv) a = (double)v0[r < kRowsCached ? r : 0] * w0 +
+                                           (double)v1[r < kRowsCached ? r : 0] * w1;
+        else if (r == nv) a = w0 * w0 + w1 * w1;
+        red[u][tid] = a;
+      }
+      __syncthreads();
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) s += red[ru][rl * 8 + m];
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      if (rl == 0 && r0 + ru < rows) I.part[(int64_t)(r0 + ru) * I.ntile + t] = s;
+      __syncthreads();
+    }
+  }
+}
+
 // Gram-Schmidt pass 2, only where gs_refine asks for it (else the workgroup
 // returns at once and the fold writes zeros): t = w - sum_{r <= j} h_r
 // sigma_r V_r (h and ||w||^2 in row coff) in registers, w itself untouched,
 // then the partials of V_r . t (r <= j).  This variant keeps each lane's
 // entries of V_0..V_j in registers between the subtraction and the dots (one
 // read of the basis instead of two); for instances with j + 1 <= kRowsCached.
-constexpr int kRowsCached = 32;
 
 template <class T>
 __global__ void __launch_bounds__(256) kb_axpy_dots_cached(const InstDesc<T>* __restrict__ ds, BatchSet A,

@@ -687,43 +687,68 @@ __global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, co
   jac_columns_elem<D, P, T>(W, trW, blocks, m, p, blockIdx.x);
 }
 
-// Inverse of one diagonal block per workgroup: LU with partial pivoting, then
-// lane k solves L U y = P e_k for column k of the inverse.  Each lane keeps
-// one row of the block in registers through the elimination; the pivot row of
-// a step goes through LDS once and every other lane reads it as a broadcast,
-// so the elimination runs on registers.  Rows are not swapped: a lane that
-// supplied the pivot of step k holds row k of the factors, pr[k] its
-// original index.  The LU factors then go to LDS in pivot order for the
-// column solves (uniform, broadcast reads).
+// Inverse of one diagonal block per workgroup: Gauss-Jordan elimination with
+// partial pivoting on [A | I], in place.  Each lane keeps one row in
+// registers.  Rows are never swapped: the lane whose row supplies the pivot of
+// step k (largest |entry| in the current column among the rows not yet used,
+// lowest row on ties) supplies it to the other lanes, which subtract its
+// multiple: by lane reads into scalar registers when the block fits one wave,
+// through LDS (one barrier per step) when it spans two.  The register row is rotated by one position per step, so the
+// current column is always register 0 and the step body is the same for every
+// step (a loop, not BS unrolled copies): position j takes the updated entry of
+// position j + 1, and the last position takes the new column of the right-hand
+// part.  Pivot rows are not normalised when chosen; each lane divides its row
+// by its own pivot at the end, which commutes with the later eliminations.
+// After BS steps the lane that supplied pivot k holds row k of the inverse,
+// its position k' the column piv[k'].
 // The inverse is written element-fastest, Ainv[(row * BS + col) * n + e], so
 // the preconditioner apply is a coalesced batched mat-vec.  It is stored in
 // FP32 for both state precisions: the preconditioner only steers GMRES (the
 // Krylov residual uses the exact Jacobian), and its apply reads half the bytes.
+// Consecutive elements run on one XCD, so the elements that share a line of
+// the output fill it in the same L2.
 template <int BS>
 constexpr int inv_threads() { return 64 * ((BS + 63) / 64); }
+// waves per SIMD the inversion is compiled for (FP64 rows of 70 fit 3)
+template <int BS, class T>
+constexpr int inv_waves() { return BS > 64 && sizeof(T) == 8 ? 3 : 4; }
+
+// the value v holds in lane l of the wave (l wave-uniform), as a scalar
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 template <int BS, class T>
 __device__ __forceinline__ void block_inverse_elem(const T* __restrict__ A, float* __restrict__ Ainv, int n, int e) {
-  constexpr int LD = BS + 1;
   constexpr int NT = inv_threads<BS>();
   constexpr int NW = NT / 64;
-  __shared__ T a[BS * LD];
-  __shared__ T prow[BS];
-  __shared__ int pr[BS];
-  __shared__ T wbest[NW];
-  __shared__ int wbi[NW];
+  // per-wave pivot candidates (value, row, the row itself), double-buffered
+  // by step parity so that one barrier per step suffices
+  __shared__ T crow[2][NW][BS];
+  __shared__ T cval[2][NW];
+  __shared__ int cidx[2][NW];
+  __shared__ int piv[BS];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const bool own = t < BS;
-  const T* src = A + (size_t)e * BS * BS;
+  const T* src = A + (size_t)e * BS * BS + (size_t)(own ? t : 0) * BS;
   T r[BS];
 #pragma unroll
-  for (int j = 0; j < BS; ++j) r[j] = own ? src[(size_t)t * BS + j] : T(0);
-  bool done = !own;
+  for (int j = 0; j < BS; ++j) r[j] = own ? src[j] : T(0);
+  bool used = !own;
   int myk = 0;
-#pragma unroll
+  T dp = T(1);  // the lane's own pivot value
   for (int k = 0; k < BS; ++k) {
-    // pivot: largest |a[i][k]| over the rows not yet used (lowest row on ties)
-    T best = done ? T(-1) : fabs(r[k]);
+    const int buf = k & 1;
+    // a NaN entry counts as the largest, so the pivot is always a row not yet
+    // used (every row is used exactly once and piv[] stays a permutation)
+    T best = used ? T(-1) : fabs(r[0]);
+    if (best != best) best = T(INFINITY);
     int bi = t;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -731,63 +756,54 @@ __device__ __forceinline__ void block_inverse_elem(const T* __restrict__ A, floa
       const int oi = __shfl_xor(bi, off);
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    if constexpr (NW > 1) {
-      if (lane == 0) { wbest[wv] = best; wbi[wv] = bi; }
+    if constexpr (NW == 1) {
+      // one wave: the pivot row is read from the pivot lane's registers into
+      // scalar registers (no LDS traffic and no barrier per step)
+      bi = __builtin_amdgcn_readfirstlane(bi);
+      const bool me = t == bi;
+      const T d = lane_value(r[0], bi);
+      if (me) { used = true; myk = k; dp = d; }
+      if (t == 0) piv[k] = bi;
+      const T f = me ? T(0) : r[0] / d;
+#pragma unroll
+      for (int j = 0; j + 1 < BS; ++j) r[j] = r[j + 1] - f * lane_value(r[j + 1], bi);
+      r[BS - 1] = me ? T(1) : -f;
+    } else {
+      if (t == bi) {
+#pragma unroll
+        for (int j = 0; j < BS; ++j) crow[buf][wv][j] = r[j];
+      }
+      if (lane == 0) { cval[buf][wv] = best; cidx[buf][wv] = bi; }
       __syncthreads();
-      best = wbest[0];
-      bi = wbi[0];
+      int w = 0;
+      best = cval[buf][0];
+      bi = cidx[buf][0];
 #pragma unroll
-      for (int w = 1; w < NW; ++w)
-        if (wbest[w] > best || (wbest[w] == best && wbi[w] < bi)) { best = wbest[w]; bi = wbi[w]; }
-    }
-    if (t == bi) {
+      for (int u = 1; u < NW; ++u)
+        if (cval[buf][u] > best || (cval[buf][u] == best && cidx[buf][u] < bi)) { best = cval[buf][u]; bi = cidx[buf][u]; w = u; }
+      const T* prow = crow[buf][w];
+      const bool me = t == bi;
+      if (me) { used = true; myk = k; dp = prow[0]; }
+      if (t == 0) piv[k] = bi;
+      const T f = me ? T(0) : r[0] / prow[0];
 #pragma unroll
-      for (int j = k; j < BS; ++j) prow[j] = r[j];
-      pr[k] = t;
-      myk = k;
-      done = true;
+      for (int j = 0; j + 1 < BS; ++j) r[j] = r[j + 1] - f * prow[j + 1];
+      r[BS - 1] = me ? T(1) : -f;
     }
-    __syncthreads();
-    if (!done) {
-      const T l = r[k] / prow[k];
-      r[k] = l;
-#pragma unroll
-      for (int j = k + 1; j < BS; ++j) r[j] -= l * prow[j];
-    }
-    __syncthreads();
   }
-  if (own)
-#pragma unroll
-    for (int j = 0; j < BS; ++j) a[myk * LD + j] = r[j];
   __syncthreads();
-  // columns of the inverse: A^{-1} e_k = U^{-1} L^{-1} P e_k, (P e_k)[r] = [pr[r] == k]
-  for (int k = t; k < BS; k += NT) {
-    T y[BS];
+  if (own) {
+    const T s = T(1) / dp;
+    float* dst = Ainv + (size_t)myk * BS * n + e;
 #pragma unroll
-    for (int r2 = 0; r2 < BS; ++r2) y[r2] = pr[r2] == k ? T(1) : T(0);
-#pragma unroll
-    for (int r2 = 1; r2 < BS; ++r2) {
-      T s2 = y[r2];
-#pragma unroll
-      for (int c = 0; c < r2; ++c) s2 -= a[r2 * LD + c] * y[c];
-      y[r2] = s2;
-    }
-#pragma unroll
-    for (int r2 = BS - 1; r2 >= 0; --r2) {
-      T s2 = y[r2];
-#pragma unroll
-      for (int c = r2 + 1; c < BS; ++c) s2 -= a[r2 * LD + c] * y[c];
-      y[r2] = s2 / a[r2 * LD + r2];
-    }
-#pragma unroll
-    for (int r2 = 0; r2 < BS; ++r2) Ainv[((size_t)r2 * BS + k) * n + e] = (float)y[r2];
+    for (int j = 0; j < BS; ++j) dst[(size_t)piv[j] * n] = (float)(r[j] * s);
   }
 }
 
 template <int BS, class T>
-__global__ void __launch_bounds__(inv_threads<BS>()) k_block_inverse(const T* __restrict__ A, float* __restrict__ Ainv,
+__global__ void __launch_bounds__(inv_threads<BS>(), (inv_waves<BS, T>())) k_block_inverse(const T* __restrict__ A, float* __restrict__ Ainv,
                                                                      int n) {
-  block_inverse_elem<BS, T>(A, Ainv, n, blockIdx.x);
+  block_inverse_elem<BS, T>(A, Ainv, n, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // y = blockdiag(A_e)^{-1} x: one lane per (row, element), element fastest.
