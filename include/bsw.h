@@ -122,7 +122,8 @@ typedef struct {
                               [gmres_rtol, forcing_max] */
   double cfl, t_end, dt;
   int32_t max_steps;       /* < 0: all steps */
-  int32_t timing;          /* nonzero: time every Jacobian-apply launch with HIP events */
+  int32_t timing;          /* nonzero: time the Jacobian applies of every fourth Arnoldi step
+                            * with HIP events (events on every apply would slow the solve) */
   double forcing_max;      /* largest GMRES relative tolerance of a Newton system (the
                               forcing term's ceiling); <= 0 selects 3e-2 */
   int32_t cont_steps;      /* continuation on gamma (Sec. 6.3): n >= 2 Newton solves per

@@ -610,6 +610,11 @@ struct BatchEngine {
   hipEvent_t tick_ev[2] = {nullptr, nullptr};
   hipEvent_t jt0[2] = {nullptr, nullptr}, jt1[2] = {nullptr, nullptr};
   bool timing = false;
+  // in timing mode the Jacobian apply of every kTimeEvery-th tick carries
+  // HIP events (events on every apply would add their own cost to the solve)
+  static constexpr int kTimeEvery = 4;
+  int64_t tick_no = 0;
+  bool timed_tick[2] = {false, false};
   double jac_seconds = 0.0, jac_launches = 0.0;
   // host time issuing Arnoldi steps and waiting for them (timing mode)
   double issue_seconds = 0.0, wait_seconds = 0.0, arnoldi_steps = 0.0;
@@ -637,6 +642,8 @@ struct BatchEngine {
     const std::vector<int>* jv = &tk.jv;
     const int pa = tk.parity;
     const int offA = pa ? kScA1 : kScA, offB = pa ? kScB1 : kScB;
+    const bool tm = timing && tick_no++ % kTimeEvery == 0;
+    timed_tick[pa] = tm;
     BatchSet S;
     // z = sigma_j M^{-1} V_j
     int nt = build(S, L, K_ITEM, jv);
@@ -651,13 +658,13 @@ struct BatchEngine {
     // w = J z (face traces of z, then the element pass)
     nt = build(S, L, K_TRACE, jv);
     auto fj = [&]<int D, int PP, class TT>() -> int {
-      hipExtLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, timing ? jt0[pa] : nullptr,
+      hipExtLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, tm ? jt0[pa] : nullptr,
                             nullptr, 0, d_desc, S, (int)B_Z, 2);
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
     if (int rc = dispatchT<T>(dim, P, fj)) return rc;
-    if (int rc = elem_pass(1, L, jv, (int)B_W, (int)B_Z, (int)B_WK, timing ? jt1[pa] : nullptr)) return rc;
+    if (int rc = elem_pass(1, L, jv, (int)B_W, (int)B_Z, (int)B_WK, tm ? jt1[pa] : nullptr)) return rc;
     --launches;  // counted in the tick's nine
     // pass 1: h1 = V^T w and w . w
     nt = build(S, L, K_VEC, jv);
@@ -818,7 +825,7 @@ struct BatchEngine {
           arnoldi_steps += 1;
         }
         ++ticks;
-        if (timing) {
+        if (timing && timed_tick[cur.parity]) {
           float ms = 0.f;
           if (hipEventElapsedTime(&ms, jt0[cur.parity], jt1[cur.parity]) == hipSuccess) {
             jac_seconds += 1e-3 * ms;
