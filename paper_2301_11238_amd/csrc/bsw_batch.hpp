@@ -594,10 +594,12 @@ struct BatchEngine {
   // second pass where the first cancelled more than half of the squared norm
   // (gs_refine, decided on the device per instance), per instance:
   // J x = rhs to ||rhs - J x|| <= rtol ||rhs|| with x = B_DW starting at 0.
-  // One Arnoldi step of every participating instance is nine launches
+  // One Arnoldi step of every participating instance is eight launches
   // (preconditioner, traces, Jacobian, dots with ||w||^2, the second pass
-  // (an immediate return where it is not needed), new vector and its norm,
-  // and a fold kernel after each of the three reductions); the
+  // (an immediate return where it is not needed), new vector with its norm
+  // partials, and a fold kernel after each of the two Gram-Schmidt
+  // reductions; the norm partials are folded by the next step's
+  // preconditioner pass); the
   // Hessenberg column, Givens rotations and the cycle test run on the host
   // from the mapped scalars.  The host issues step t+1 before it reads step
   // t (Krylov index and iteration cap known in advance), so the device never
@@ -637,7 +639,28 @@ struct BatchEngine {
     }
   }
 
-  int launch_tick(const Tick& tk) {
+  // The norm of V_{j+1} (from the partials of kb_normalize) is folded by the
+  // next step's preconditioner pass, which needs sigma_{j+1} first; for an
+  // instance without a next step, close_norms folds it on its own.  A step's
+  // completion event is recorded after those folds.
+  int close_norms(const Tick& prev, const std::vector<int>& keep) {
+    std::vector<int> L, jv;
+    for (size_t a = 0; a < prev.mem.size(); ++a)
+      if (std::find(keep.begin(), keep.end(), prev.mem[a]) == keep.end()) {
+        L.push_back(prev.mem[a]);
+        jv.push_back(prev.jv[a]);
+      }
+    if (!L.empty()) {
+      const std::vector<int> rows(L.size(), 1);
+      if (int rc = final_rows(L, rows, 0, 0u, kScN + prev.parity, 0, 1, &jv)) return rc;
+    }
+    HIPCHK(c, hipEventRecord(tick_ev[prev.parity], c->stream));
+    return BSW_OK;
+  }
+
+  // one pipelined Arnoldi step of the instances in tk; prev: the step issued
+  // before it (its norms are folded here), or null
+  int launch_tick(const Tick& tk, const Tick* prev) {
     const std::vector<int>& L = tk.mem;
     const std::vector<int>* jv = &tk.jv;
     const int pa = tk.parity;
@@ -645,16 +668,21 @@ struct BatchEngine {
     const bool tm = timing && tick_no++ % kTimeEvery == 0;
     timed_tick[pa] = tm;
     BatchSet S;
-    // z = sigma_j M^{-1} V_j
+    // z = sigma_j M^{-1} V_j, sigma_j folded here for instances continuing prev
     int nt = build(S, L, K_ITEM, jv);
+    for (size_t a = 0; a < L.size(); ++a)
+      S.rows[a] = prev && std::find(prev->mem.begin(), prev->mem.end(), L[a]) != prev->mem.end() ? 1 : 0;
+    const int offN = kScN + (prev ? prev->parity : 0);
     auto fp = [&]<int D, int PP, class TT>() -> int {
       using Sh = Shape<D, PP>;
-      hipLaunchKernelGGL((kb_prec_krylov<Sh::BS, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S,
-                         (const double*)sc, (int)B_V0, (int)B_Z);
+      hipLaunchKernelGGL((kb_prec_krylov<Sh::BS, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sc, sch_dev,
+                         offN, (int)B_V0, (int)B_Z);
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
     if (int rc = dispatchT<T>(dim, P, fp)) return rc;
+    if (prev)
+      if (int rc = close_norms(*prev, L)) return rc;
     // w = J z (face traces of z, then the element pass)
     nt = build(S, L, K_TRACE, jv);
     auto fj = [&]<int D, int PP, class TT>() -> int {
@@ -665,7 +693,7 @@ struct BatchEngine {
     };
     if (int rc = dispatchT<T>(dim, P, fj)) return rc;
     if (int rc = elem_pass(1, L, jv, (int)B_W, (int)B_Z, (int)B_WK, tm ? jt1[pa] : nullptr)) return rc;
-    --launches;  // counted in the tick's nine
+    --launches;  // counted with the tick's own launches below
     // pass 1: h1 = V^T w and w . w
     nt = build(S, L, K_VEC, jv);
     int maxrows = 0;
@@ -689,14 +717,11 @@ struct BatchEngine {
     HIPCHK(c, hipGetLastError());
     for (auto& r : rows) r -= 1;
     if (int rc = final_rows(L, rows, 0, 0u, offB, 1, -1, jv, offA)) return rc;
-    // V_{j+1} = w - V (h1 + h2) and its norm (sigma_{j+1} = 1 / norm)
+    // V_{j+1} = w - V (h1 + h2) and the partials of its squared norm
     hipLaunchKernelGGL((kb_normalize<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
                        offB, (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
-    std::fill(rows.begin(), rows.end(), 1);
-    if (int rc = final_rows(L, rows, 0, 0u, kScN + pa, 0, 1, jv)) return rc;
-    launches += 9;
-    HIPCHK(c, hipEventRecord(tick_ev[pa], c->stream));
+    launches += 6;  // prec, trace, element pass, dots, second pass, normalize (folds count themselves)
     return BSW_OK;
   }
 
@@ -781,7 +806,7 @@ struct BatchEngine {
     }
     cur.parity = parity;
     if (!cur.mem.empty())
-      if (int rc = launch_tick(cur)) return rc;
+      if (int rc = launch_tick(cur, nullptr)) return rc;
     std::vector<int> rejoin, E;
     std::vector<char> dropped(kMaxBatch, 0);
     while (!cur.mem.empty() || !rejoin.empty()) {
@@ -814,8 +839,10 @@ struct BatchEngine {
         }
         nxt = sorted;
         const auto h0 = std::chrono::steady_clock::now();
-        if (int rc = launch_tick(nxt)) return rc;
+        if (int rc = launch_tick(nxt, cur.mem.empty() ? nullptr : &cur)) return rc;
         if (timing) issue_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
+      } else if (!cur.mem.empty()) {
+        if (int rc = close_norms(cur, {})) return rc;
       }
       if (!cur.mem.empty()) {
         const auto h0 = std::chrono::steady_clock::now();

@@ -498,9 +498,16 @@ __global__ void __launch_bounds__(256) kb_normalize(const InstDesc<T>* __restric
 }
 
 // z = sigma_j M^{-1} V_j (the preconditioner on the stored Krylov vector j)
+// Where A.rows[ai] is set, V_j was written by the previous step's
+// kb_normalize and its squared-norm partials are still in I.part: every
+// workgroup folds them (the fold of kb_rows_final, same order) into
+// sigma_j = 1 / ||V_j||, and the instance's first workgroup stores sigma_j and
+// the norm (row offN) in sc and its host mirror sch.  Elsewhere sigma_j is
+// read from sc.
 template <int BS, class T>
 __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restrict__ ds, BatchSet A,
-                                                       const double* __restrict__ sc, int sV0, int sZ) {
+                                                       double* __restrict__ sc, double* __restrict__ sch, int offN,
+                                                       int sV0, int sZ) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int ai = bset_find(A, b);
   const int slot = A.inst[ai];
@@ -509,8 +516,24 @@ __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restr
   const int n = I.m.n_el;
   int row, e;
   row_tile<BS>(b - A.tile0[ai], row, e);
+  double sgm;
+  if (A.rows[ai]) {
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < I.ntile; t += 256) acc += I.part[t];
+    const double x = sqrt(bred(acc, 0));
+    sgm = x > 0.0 ? 1.0 / x : 0.0;
+    if (b == A.tile0[ai] && threadIdx.x == 0) {
+      double* s = sc + (int64_t)slot * kScStride;
+      double* sh = sch + (int64_t)slot * kScStride;
+      s[kScS + j] = sgm;
+      sh[kScS + j] = sgm;
+      s[offN] = x;
+      sh[offN] = x;
+    }
+  } else {
+    sgm = sc[(int64_t)slot * kScStride + kScS + j];
+  }
   if (e >= n) return;
-  const double sgm = sc[(int64_t)slot * kScStride + kScS + j];
   const T* x = bslot(I, sV0, 0) + (int64_t)j * I.ld;
   const float* Ai = I.blk + (size_t)row * BS * n + e;
   double s = 0.0;
