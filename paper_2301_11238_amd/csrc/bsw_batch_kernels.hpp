@@ -516,30 +516,35 @@ __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restr
   const int n = I.m.n_el;
   int row, e;
   row_tile<BS>(b - A.tile0[ai], row, e);
-  double sgm;
-  if (A.rows[ai]) {
-    double acc = 0.0;
+  // the loads of the norm partials and of the block row times V_j go out
+  // before sigma is reduced (the product does not depend on it)
+  const bool fold = A.rows[ai] != 0;
+  double acc = 0.0;
+  if (fold)
     for (int t = threadIdx.x; t < I.ntile; t += 256) acc += I.part[t];
-    const double x = sqrt(bred(acc, 0));
-    sgm = x > 0.0 ? 1.0 / x : 0.0;
+  double s = 0.0;
+  if (e < n) {
+    const T* x = bslot(I, sV0, 0) + (int64_t)j * I.ld;
+    const float* Ai = I.blk + (size_t)row * BS * n + e;
+#pragma unroll
+    for (int c = 0; c < BS; ++c) s += (double)Ai[(size_t)c * n] * (double)x[(size_t)c * n + e];
+  }
+  double sgm;
+  if (fold) {
+    const double nrm = sqrt(bred(acc, 0));
+    sgm = nrm > 0.0 ? 1.0 / nrm : 0.0;
     if (b == A.tile0[ai] && threadIdx.x == 0) {
-      double* s = sc + (int64_t)slot * kScStride;
+      double* sd = sc + (int64_t)slot * kScStride;
       double* sh = sch + (int64_t)slot * kScStride;
-      s[kScS + j] = sgm;
+      sd[kScS + j] = sgm;
       sh[kScS + j] = sgm;
-      s[offN] = x;
-      sh[offN] = x;
+      sd[offN] = nrm;
+      sh[offN] = nrm;
     }
   } else {
     sgm = sc[(int64_t)slot * kScStride + kScS + j];
   }
-  if (e >= n) return;
-  const T* x = bslot(I, sV0, 0) + (int64_t)j * I.ld;
-  const float* Ai = I.blk + (size_t)row * BS * n + e;
-  double s = 0.0;
-#pragma unroll 7
-  for (int c = 0; c < BS; ++c) s += (double)Ai[(size_t)c * n] * (double)x[(size_t)c * n + e];
-  bslot(I, sZ, 0)[(size_t)row * n + e] = (T)(sgm * s);
+  if (e < n) bslot(I, sZ, 0)[(size_t)row * n + e] = (T)(sgm * s);
 }
 
 // ------------------------------------------------------------------ per-instance reductions
