@@ -44,6 +44,8 @@ def parse():
                     help="c2: the 8192-triangle P2 incline (default); c3: the 131072-triangle P3 mesh of the "
                          "circular dam break (kernel timings only)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed leg of the solve")
+    ap.add_argument("--no-hbm-resident", action="store_true",
+                    help="skip the operator and Jacobian applies cycled through >= 2 GiB of buffer sets")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving comparison (batched FP32 server vs plain FP64 solves)")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -88,6 +90,95 @@ def time_kernel(fn, stream, reps=20):
     end.record(stream)
     end.synchronize()
     return start.elapsed_time(end) / 1e3 / reps
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second), median."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    del src, dst
+    return 2 * nbytes / sorted(ts)[len(ts) // 2]
+
+
+def median_call_seconds(fn, count, stream):
+    """Median HIP-event duration of fn(i), i = 0 .. count - 1, each call
+    bracketed by its own events on the library's stream."""
+    import torch
+    fn(0)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(count)]
+    for i in range(count):
+        ev[i][0].record(stream)
+        fn(i)
+        ev[i][1].record(stream)
+    ev[-1][1].synchronize()
+    ts = sorted(a.elapsed_time(b) / 1e3 for a, b in ev)
+    return ts[len(ts) // 2]
+
+
+def hbm_resident(problem, mesh, disc, cp, dt, stream, op_bytes, jac_bytes, min_total=2 << 30):
+    """Operator and Jacobian applies whose working sets cycle through enough
+    independent buffer sets (>= 2 GiB in all) that every call finds its data
+    evicted from the 256 MB Infinity Cache and reads it from HBM; the median
+    of per-call event times.  Operator sets: (W, b_old, R) on one
+    discretisation.  Jacobian sets: one discretisation per set, linearised
+    at its own W, with its own x and y (the traces of W and x are per set)."""
+    import math as _m
+    import torch
+    import workloads as wl
+    from paper_2301_11238_amd import bsw
+    n_el, P = disc.n_el, problem.P
+    base = [torch.from_numpy(wl.random_state(2, P, n_el, 900 + k)).cuda() for k in range(4)]
+    b0 = disc.step_begin(cp, dt, base[0])
+    vec = base[0].numel() * 8
+    # operator
+    k_op = max(8, _m.ceil(min_total / (2 * vec + b0.numel() * 8)))
+    Ws = [base[k % 4].clone() for k in range(k_op)]
+    Bs = [disc.step_begin(cp, dt, Ws[k]) for k in range(k_op)]
+    Rs = [disc.empty() for _ in range(k_op)]
+    t_op = median_call_seconds(lambda i: disc.operator_apply(cp, dt, Ws[i % k_op], Bs[i % k_op], Rs[i % k_op]),
+                               max(64, 2 * k_op), stream)
+    op_set = 2 * vec + b0.numel() * 8
+    del Bs, Rs
+    # Jacobian
+    nfp = disc.nf * 3 * (P + 1) * n_el * 8          # face traces of one vector (3 faces, P + 1 points)
+    jac_set = 3 * vec + 2 * nfp
+    k_j = max(8, _m.ceil(min_total / jac_set))
+    discs, xs, ys = [], [], []
+    for k in range(k_j):
+        d = bsw.Disc(mesh, P, bsw.BSW_FP64)
+        W = Ws[k % k_op] if k < k_op else base[k % 4].clone()
+        Ws.append(W)
+        d.jacobian_linearize(cp, dt, W)
+        discs.append(d)
+        xs.append(torch.randn_like(W))
+        ys.append(d.empty())
+    t_j = median_call_seconds(lambda i: discs[i % k_j].jacobian_apply(xs[i % k_j], ys[i % k_j]),
+                              max(64, 2 * k_j), stream)
+    for d in discs:
+        d.close()
+    del discs, xs, ys, Ws
+    torch.cuda.synchronize()
+    copy = copy_bandwidth()
+
+    def row(t, nbytes, k, set_bytes):
+        return {"buffer_sets": k, "working_set_GiB": k * set_bytes / 2 ** 30, "median_us": 1e6 * t,
+                "GB/s": nbytes / t / 1e9, "frac_of_8TBs": nbytes / t / 8e12, "frac_of_copy": nbytes / t / copy,
+                "element_applies_per_s": n_el / t}
+    return {"operator": row(t_op, op_bytes, k_op, op_set), "jacobian_apply": row(t_j, jac_bytes, k_j, jac_set),
+            "copy_GB/s": copy / 1e9,
+            "note": "algorithmic bytes per call over the median per-call time, data cycled through >= 2 GiB "
+                    "of buffer sets so it comes from HBM; the `kernels` section is the same calls on one "
+                    "buffer set (Infinity-Cache resident)"}
 
 
 def cpu_baseline(problem, seconds):
@@ -322,6 +413,9 @@ def main():
                       "autotuned tile shape)",
             "bytes_per_launch": k["bytes"], "launch_seconds": k["seconds"],
             "launches_timed": st.get("jac_apply_launches", 0)}
+    hbm = None
+    if not args.kernels_only and not args.no_hbm_resident:
+        hbm = hbm_resident(problem, mesh, disc, cp, dt, stream, op_bytes, jac_bytes)
     if args.kernels_only:
         print(json.dumps({"workload": args.workload, "n_el": n_el, "P": problem.P,
                           "kernels": {n: {"ms": 1e3 * v["seconds"], "GB/s": v["bytes"] / v["seconds"] / 1e9}
@@ -351,7 +445,7 @@ def main():
                    "gmres_per_step": st["gmres_total"] / max(1, st["steps"]),
                    "capped_steps": st["capped"],
                    "applies_per_step": applies / max(1, st["steps"]),
-                   # per pipelined Arnoldi step (nine launches): host time to issue it and
+                   # per pipelined Arnoldi step (eight launches): host time to issue it and
                    # host time blocked on its results; issue < step time means the launch
                    # path is not the limit (the device is)
                    "arnoldi_step_us": 1e6 * el / max(1.0, st["arnoldi_steps"]) if st["arnoldi_steps"] else None,
@@ -362,6 +456,7 @@ def main():
         "fp32_mixed": fp32 if not args.no_fp32 else None,
         "kernels": {name: {"ms": 1e3 * v["seconds"], "GB/s": v["bytes"] / v["seconds"] / 1e9}
                     for name, v in kern.items()},
+        "hbm_resident": hbm,
         "tile_autotuner": [{"pass": "jacobian" if r["mode"] else "residual",
                             "precision": "f64" if r["bytes"] == 8 else "f32", "size_class": r["size_class"],
                             "lanes": r["lanes"],
