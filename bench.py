@@ -238,6 +238,63 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
 
+def overload(ctx, steps, rate=200.0, window_s=1.0, max_admitted=32, dof_cap=4.0e6, deadline_s=90.0):
+    """The stated request stream above capacity, with a bounded admission
+    window: Poisson arrivals at `rate` per second for `window_s` seconds
+    (2 % of them large 999,698-triangle P2 incline runs).  A large run is
+    rejected for exceeding the per-request cap of `dof_cap` DOFs; any other
+    arrival is admitted to the batched FP32 server while fewer than
+    `max_admitted` admitted requests are unfinished, and rejected otherwise.
+    Admitted requests are drawn from the serving mix (512-8192 triangles, P
+    1-3, regs 1-3), cut to `steps` time steps; those still unfinished
+    `deadline_s` after the first arrival are cancelled and counted."""
+    import numpy as np
+    import workloads as wl
+    from paper_2301_11238_amd import bsw
+    arrivals = wl.config5_arrivals(rate=rate, duration=window_s)
+    srv = bsw.Server(ctx, 128 << 30, 128)
+    admitted, rej_full, rej_large = [], 0, 0
+    t0 = time.perf_counter()
+    try:
+        for ta, kind, k in arrivals:
+            dtw = t0 + ta - time.perf_counter()
+            if dtw > 0:
+                time.sleep(dtw)
+            if kind == "large":          # 999,698 x 42 DOFs
+                rej_large += 1
+                continue
+            live = sum(1 for t, _ in admitted if srv.poll(t) in (bsw.BSW_REQ_QUEUED, bsw.BSW_REQ_RUNNING))
+            if live >= max_admitted:
+                rej_full += 1
+                continue
+            p = wl.serving_request(2000 + k)
+            if p.n_dof > dof_cap:
+                rej_large += 1
+                continue
+            t = srv.submit(p.xy, p.el2vert, p.P, bsw.BSW_FP32, bsw.make_params(p.params), ic=p.ic,
+                           opts=bsw.Options(t_end=p.t_end, cfl=p.cfl, max_steps=steps))
+            admitted.append((t, ta))
+        lat, done, unfinished = [], 0, 0
+        for t, ta in admitted:
+            left = deadline_s - (time.perf_counter() - t0)
+            if srv.wait(t, max(left, 0.0)) == bsw.BSW_REQ_DONE:
+                _, st = srv.fetch(t)
+                lat.append(st["queue_seconds"] + st["seconds"])
+                done += 1
+            else:
+                srv.cancel(t)
+                unfinished += 1
+        T = time.perf_counter() - t0
+    finally:
+        srv.close()
+    return {"offered_rate_per_s": rate, "window_s": window_s, "offered": len(arrivals),
+            "admitted": len(admitted), "rejected_window_full": rej_full, "rejected_over_cap": rej_large,
+            "max_admitted": max_admitted, "completed": done, "cancelled_at_deadline": unfinished,
+            "achieved_solves_per_s": done / T, "seconds": T,
+            "p50_s": float(np.percentile(lat, 50)) if lat else None,
+            "p99_s": float(np.percentile(lat, 99)) if lat else None}
+
+
 def serving(ctx, n_req, steps):
     """Batched FP32 solve server against plain one-solve-at-a-time FP64 solves
     on the same request list: slope flows and dam breaks of 512-8192
@@ -465,6 +522,7 @@ def main():
     }
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests, args.serve_steps)
+        out["serving"]["overload"] = overload(ctx, args.serve_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
     print(json.dumps(out))
