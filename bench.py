@@ -199,9 +199,47 @@ def cpu_baseline(problem, seconds):
         applies += 2
     el = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=n_dof * applies / el, unit="DOF-updates/s", cores=threads, kind="oracle",
-                sample=f"{applies} whole-mesh applies (operator + Jacobian, alternating) of the FP64 C oracle "
-                       f"on the same 8192-triangle P2 mesh, {el:.1f} s")
+    out = dict(value=n_dof * applies / el, unit="DOF-updates/s", cores=threads, kind="oracle",
+               sample=f"{applies} whole-mesh applies (operator + Jacobian, alternating) of the FP64 C oracle "
+                      f"on the same 8192-triangle P2 mesh, {el:.1f} s")
+    out["cpu_model"] = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                             if ln.startswith("model name")), None) if os.path.exists("/proc/cpuinfo") else None
+    out["nproc"] = os.cpu_count()
+    # the same sample on one core, in a child process started with one OpenMP thread
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r); import bench, workloads as wl; "
+            "p = wl.config2(wl.REG1, 1e-3); r = bench.cpu_baseline_applies(p, %f); print(r)") % (ROOT, seconds / 3)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+        out["one_core_value"] = float(res.stdout.strip().splitlines()[-1])
+    except Exception:  # reported as missing rather than failing the bench
+        out["one_core_value"] = None
+    # one full solve of the 1-D dam break (200 P1 elements, reg 1, 314 steps to t = 1)
+    c1 = wl.config1(wl.REG1)
+    o1 = oracle.Oracle(c1.dim, c1.P, c1.xy, c1.el2vert)
+    t1 = time.perf_counter()
+    o1.solve(c1.params, o1.project_ic(c1.ic), oracle.SolveOptions(t_end=c1.t_end, cfl=c1.cfl))
+    out["c1_solves_per_s"] = 1.0 / (time.perf_counter() - t1)
+    return out
+
+
+def cpu_baseline_applies(problem, seconds):
+    """DOF-updates/s of the oracle's alternating operator and Jacobian applies
+    (the all-core measure of cpu_baseline, for a child run on one core)."""
+    import oracle
+    import workloads as wl
+    orc = oracle.Oracle(problem.dim, problem.P, problem.xy, problem.el2vert)
+    W = orc.project_ic(problem.ic)
+    dt = 0.01
+    b = orc.step_begin(problem.params, W, dt)
+    x = wl.random_vector(problem.dim, problem.P, orc.n_el, 1)
+    applies, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        orc.residual(problem.params, W, b, dt)
+        orc.jac_apply(problem.params, W, x, dt)
+        applies += 2
+    return W.size * applies / (time.perf_counter() - t0)
 
 
 def fp32_leg(problem, mesh, cp, dt, args, W64, el64):
