@@ -327,7 +327,7 @@ struct BatchEngine {
   // tile shape the autotuner picks for this launch's size; t_stop (optional)
   // is recorded by the launch itself when it completes.
   int elem_pass(int mode, const std::vector<int>& L, const std::vector<int>* jv, int sW, int sX, int sOut,
-                hipEvent_t t_stop = nullptr) {
+                hipEvent_t t_stop = nullptr, hipEvent_t t_start = nullptr) {
     int64_t n_el = 0;
     for (int k : L) n_el += slots[k]->n_el;
     const uint64_t key = TileTuner::key(dim, P, (int)sizeof(T), mode, n_el);
@@ -347,10 +347,10 @@ struct BatchEngine {
     auto f = [&]<int D, int PP, class TT>() -> int {
       auto go = [&]<int NT>() {
         if (mode == 0)
-          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 0, NT>), dim3(nt), dim3(NT), 0, c->stream, nullptr, t_stop, 0,
+          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 0, NT>), dim3(nt), dim3(NT), 0, c->stream, t_start, t_stop, 0,
                                 d_desc, S, sW, sX, (int)B_BOLD, sOut);
         else
-          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 1, NT>), dim3(nt), dim3(NT), 0, c->stream, nullptr, t_stop, 0,
+          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 1, NT>), dim3(nt), dim3(NT), 0, c->stream, t_start, t_stop, 0,
                                 d_desc, S, sW, sX, (int)B_BOLD, sOut);
       };
       if (v == 0) go.template operator()<kTileNT[0]>();
@@ -372,9 +372,11 @@ struct BatchEngine {
     ++launches;
     return BSW_OK;
   }
-  // mode 0: out = R(W; b_old); mode 1: out = J x (each after the trace pass of its argument)
+  // mode 0: out = R(W; b_old), after the trace pass of W; mode 1: out = J x
+  // (the element pass evaluates the neighbours' side of x itself)
   int elem(int mode, const std::vector<int>& L, int sW, int sX, int sOut) {
-    if (int rc = mode == 0 ? trace(L, sW, 1) : trace(L, sX, 2)) return rc;
+    if (mode == 0)
+      if (int rc = trace(L, sW, 1)) return rc;
     return elem_pass(mode, L, nullptr, sW, sX, sOut);
   }
   // traces of the linearisation state for all of L; diagonal blocks and their
@@ -594,9 +596,9 @@ struct BatchEngine {
   // second pass where the first cancelled more than half of the squared norm
   // (gs_refine, decided on the device per instance), per instance:
   // J x = rhs to ||rhs - J x|| <= rtol ||rhs|| with x = B_DW starting at 0.
-  // One Arnoldi step of every participating instance is eight launches
-  // (preconditioner, traces, Jacobian, dots with ||w||^2, the second pass
-  // (an immediate return where it is not needed), new vector with its norm
+  // One Arnoldi step of every participating instance is seven launches
+  // (preconditioner, Jacobian, dots with ||w||^2, the second pass (an
+  // immediate return where it is not needed), new vector with its norm
   // partials, and a fold kernel after each of the two Gram-Schmidt
   // reductions; the norm partials are folded by the next step's
   // preconditioner pass); the
@@ -683,16 +685,9 @@ struct BatchEngine {
     if (int rc = dispatchT<T>(dim, P, fp)) return rc;
     if (prev)
       if (int rc = close_norms(*prev, L)) return rc;
-    // w = J z (face traces of z, then the element pass)
-    nt = build(S, L, K_TRACE, jv);
-    auto fj = [&]<int D, int PP, class TT>() -> int {
-      hipExtLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, tm ? jt0[pa] : nullptr,
-                            nullptr, 0, d_desc, S, (int)B_Z, 2);
-      HIPCHK(c, hipGetLastError());
-      return BSW_OK;
-    };
-    if (int rc = dispatchT<T>(dim, P, fj)) return rc;
-    if (int rc = elem_pass(1, L, jv, (int)B_W, (int)B_Z, (int)B_WK, tm ? jt1[pa] : nullptr)) return rc;
+    // w = J z: one element pass (the neighbours' side of z evaluated in it)
+    if (int rc = elem_pass(1, L, jv, (int)B_W, (int)B_Z, (int)B_WK, tm ? jt1[pa] : nullptr, tm ? jt0[pa] : nullptr))
+      return rc;
     --launches;  // counted with the tick's own launches below
     // pass 1: h1 = V^T w and w . w
     nt = build(S, L, K_VEC, jv);
@@ -721,7 +716,7 @@ struct BatchEngine {
     hipLaunchKernelGGL((kb_normalize<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
                        offB, (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
-    launches += 6;  // prec, trace, element pass, dots, second pass, normalize (folds count themselves)
+    launches += 5;  // prec, element pass, dots, second pass, normalize (folds count themselves)
     return BSW_OK;
   }
 

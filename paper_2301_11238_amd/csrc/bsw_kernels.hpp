@@ -80,6 +80,26 @@ __device__ __forceinline__ void load_trace(const T* __restrict__ tr, int n, int 
   for (int f = 0; f < S::NF; ++f) X[f] = tr[(size_t)(f * NFP + kp) * n + nb];
 }
 
+// The field values at face point rr of face g of element nb, from its
+// coefficients X (the values trace_item stores, in the same arithmetic):
+// the Jacobian apply evaluates the neighbour's side of x this way instead of
+// reading a trace array written by a separate pass.
+template <int D, int P, class T>
+__device__ __forceinline__ void neighbour_values(const Tab<D, P, T>& tb, const T* __restrict__ X, int n, int nb,
+                                                 int g, int rr, T (&V)[Shape<D, P>::NF]) {
+  using S = Shape<D, P>;
+#pragma unroll
+  for (int f = 0; f < S::NF; ++f) {
+    T c[S::NP];
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i) c[i] = X[(size_t)(f * S::NP + i) * n + nb];
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i) s += tb.fphi[g][rr][i] * c[i];
+    V[f] = s;
+  }
+}
+
 // Mixed orders (Sec. 5: m1, m2, m3 for h, u and E).  The bases are ordered by
 // total degree, so field f of order m lives in the span of its first N(m)
 // modes and is tested with them; the rows of the higher modes carry the
@@ -505,7 +525,7 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
           unpack<D, T>(Xp, sp);
           if constexpr (TAN) {
             T dXp[S::NF];
-            load_trace<D, P, T>(trX, n, code >> 2, code & 3, S::NFQ - 1 - rr, dXp);
+            neighbour_values<D, P, T>(tb, x, n, code >> 2, code & 3, S::NFQ - 1 - rr, dXp);
             unpack<D, T>(dXp, dsp);
           }
         } else {

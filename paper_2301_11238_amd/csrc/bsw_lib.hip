@@ -586,26 +586,18 @@ struct StepBeginLaunch {
 struct JacApplyLaunch {
   bsw_disc d; const void* x; void* y;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional: timestamps of this dispatch
-  // the trace pass and the element pass; with events, ev_start stamps the
-  // start of the first and ev_stop the end of the second
+  // one element pass (it evaluates the neighbours' side of x itself); with
+  // events, ev_start and ev_stop stamp its start and end
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
     hipStream_t st = d->mesh->ctx->stream;
-    const dim3 gt = grid1((int64_t)Shape<D, P>::NF * Shape<D, P>::NFC * m.n_el), ge = grid1(m.n_el, Blk<D, P>::EB);
+    const dim3 ge = grid1(m.n_el, Blk<D, P>::EB);
     const T* tL = (const T*)d->trL;
-    T* tX = (T*)d->trX;
     if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
     const auto prm = devparams<T>(d->lin_prm, d->lin_dt, (const T*)d->dirtab);
-    if (ev_start) {
-      hipExtLaunchKernelGGL((k_trace<D, P, T>), gt, dim3(256), 0, st, ev_start, nullptr, 0, (const T*)x, tX, m.n_el);
-      hipExtLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), ge, dim3(256), 0, st, nullptr, ev_stop, 0,
-                            (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, tL, (const T*)tX, m, prm);
-    } else {
-      hipLaunchKernelGGL((k_trace<D, P, T>), gt, dim3(256), 0, st, (const T*)x, tX, m.n_el);
-      hipLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), ge, dim3(256), 0, st, (const T*)d->lin_W, (const T*)x,
-                         (const T*)nullptr, (T*)y, tL, (const T*)tX, m, prm);
-    }
+    hipExtLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), ge, dim3(256), 0, st, ev_start, ev_stop, 0,
+                          (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, tL, (const T*)nullptr, m, prm);
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
