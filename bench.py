@@ -30,7 +30,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
 # scaled by the same counters on a plain copy of known size; None until the
 # counters are taken on the current kernel.
-TRAFFIC_BYTES = {"jacobian_apply": 25371648.0}  # trace + element pass; counter summary under profiles/
+TRAFFIC_BYTES = {"jacobian_apply": 14595072.0}  # element pass; counter summary under profiles/
 
 
 def parse():
@@ -503,9 +503,8 @@ def main():
     lanes = tuned[0]["lanes"] if tuned else 256
     roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES.get(dominant),
-            "kernel": f"kb_trace<2,{problem.P},double> + kb_elem<2,{problem.P},double,1,{lanes}> (matrix-free "
-                      "Jacobian apply inside the solve: face traces of x, then the element pass in the "
-                      "autotuned tile shape)",
+            "kernel": f"kb_elem<2,{problem.P},double,1,{lanes}> (matrix-free Jacobian apply inside the solve: "
+                      "one element pass in the autotuned tile shape, the neighbours' side of x evaluated in it)",
             "bytes_per_launch": k["bytes"], "launch_seconds": k["seconds"],
             "launches_timed": st.get("jac_apply_launches", 0)}
     hbm = None
