@@ -372,11 +372,9 @@ struct BatchEngine {
     ++launches;
     return BSW_OK;
   }
-  // mode 0: out = R(W; b_old), after the trace pass of W; mode 1: out = J x
-  // (the element pass evaluates the neighbours' side of x itself)
+  // mode 0: out = R(W; b_old); mode 1: out = J x (the element pass evaluates
+  // the neighbours' side of its argument itself)
   int elem(int mode, const std::vector<int>& L, int sW, int sX, int sOut) {
-    if (mode == 0)
-      if (int rc = trace(L, sW, 1)) return rc;
     return elem_pass(mode, L, nullptr, sW, sX, sOut);
   }
   // traces of the linearisation state for all of L; diagonal blocks and their

@@ -110,8 +110,9 @@ __global__ void __launch_bounds__(256) kb_trace(const InstDesc<T>* __restrict__ 
     trace_item<D, P, T>(bslot(I, sX, A.jv[ai]), tr, I.m.n_el, item);
 }
 
-// MODE 0: R = residual(W; b_old) with the traces in trA; MODE 1: y = J(W) x
-// with the traces of W in trL and of x in trX
+// MODE 0: R = residual(W; b_old); MODE 1: y = J(W) x with the traces of W in
+// trL (the neighbours' side of the pass's argument, W or x, is evaluated in
+// the pass from their coefficients)
 // NT: the element-tile shape (workgroup size), chosen by the autotuner
 template <int D, int P, class T, int MODE, int NT>
 __global__ void __launch_bounds__(NT, (elem_waves<D, P, T>())) kb_elem(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW, int sX,
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(NT, (elem_waves<D, P, T>())) kb_elem(const Ins
   const int e0 = (b - A.tile0[ai]) * Blk<D, P, NT>::EB;
   elem_blocked_tile<D, P, T, MODE, NT>(bslot(I, sW, j), MODE == 1 ? bslot(I, sX, j) : nullptr,
                                    MODE == 0 ? bslot(I, sB, j) : nullptr, bslot(I, sOut, j),
-                                   MODE == 0 ? I.trA : I.trL, MODE == 1 ? I.trX : nullptr, I.m, I.p, e0);
+                                   MODE == 0 ? nullptr : I.trL, nullptr, I.m, I.p, e0);
 }
 
 template <int D, int P, class T>

@@ -422,8 +422,11 @@ struct Blk {
   static constexpr int NFF = 1 + D + D * D;                            // reals per face point
 };
 
-// MODE 0: residual (x unused, bold subtracted); MODE 1: Jacobian product
-// along x (bold unused).  One tile: elements e0 .. e0+EB-1 of one mesh.
+// MODE 0: residual (x unused, bold subtracted; trW, trX unused: the
+// neighbours' side of W is evaluated here); MODE 1: Jacobian product along x
+// (bold and trX unused; the neighbours' side of W from the linearisation's
+// traces trW, that of x evaluated here).  One tile: elements e0 .. e0+EB-1
+// of one mesh.
 template <int D, int P, class T, int MODE, int NT = 256>
 __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const T* __restrict__ x,
                                                   const T* __restrict__ bold, T* __restrict__ out,
@@ -521,7 +524,10 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
         if constexpr (TAN) unpack<D, T>(dXm, dsm);
         if (code >= 0) {
           T Xp[S::NF];
-          load_trace<D, P, T>(trW, n, code >> 2, code & 3, S::NFQ - 1 - rr, Xp);
+          // residual: the neighbour's side of W evaluated here; Jacobian:
+          // from the linearisation's traces of W
+          if constexpr (TAN) load_trace<D, P, T>(trW, n, code >> 2, code & 3, S::NFQ - 1 - rr, Xp);
+          else neighbour_values<D, P, T>(tb, W, n, code >> 2, code & 3, S::NFQ - 1 - rr, Xp);
           unpack<D, T>(Xp, sp);
           if constexpr (TAN) {
             T dXp[S::NF];

@@ -561,10 +561,9 @@ struct OpLaunch {
     auto m = view<T>(d);
     hipStream_t st = d->mesh->ctx->stream;
     if (int rc = sync_dirtab<T>(d, *p)) return rc;
-    hipLaunchKernelGGL((k_trace<D, P, T>), grid1((int64_t)Shape<D, P>::NF * Shape<D, P>::NFC * m.n_el), dim3(256), 0,
-                       st, (const T*)W, (T*)d->trA, m.n_el);
+    // one element pass: it evaluates the neighbours' side of W itself
     hipLaunchKernelGGL((k_elem_blocked<D, P, T, 0>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0, st, (const T*)W,
-                       (const T*)nullptr, (const T*)bold, (T*)R, (const T*)d->trA, (const T*)nullptr, m,
+                       (const T*)nullptr, (const T*)bold, (T*)R, (const T*)nullptr, (const T*)nullptr, m,
                        devparams<T>(*p, dt, (const T*)d->dirtab));
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
