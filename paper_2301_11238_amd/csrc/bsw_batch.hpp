@@ -136,7 +136,7 @@ int64_t instance_bytes(int64_t n_el, int dim, int P, int precision, int M) {
   const int64_t ntile = (len + kVT - 1) / kVT, ntile_e = (n_el + 255) / 256;
   int64_t b = (kBaseSlots + M + 1) * ld * w;
   b += bs * bs * n_el * (w + 4);  // diagonal blocks and their FP32 inverses
-  b += 3 * nf * nfp * n_el * w;  // face traces
+  b += nf * nfp * n_el * w;  // face traces of the linearisation state
   b += std::max<int64_t>(std::max<int64_t>(66 * ntile, 4 * ntile_e), 4096) * 8;
   const int64_t geo = dim * dim + 1 + (dim + 1) * (dim + 1);
   b += n_el * ((dim + 1) * 4 + (dim + 1) * dim * 8 + geo * 8 + (precision == BSW_FP32 ? geo * 4 : 0));
@@ -310,13 +310,13 @@ struct BatchEngine {
     ++launches;
     return dispatchT<T>(dim, P, f);
   }
-  // face traces of slot sX into trace set `which` (0 linearisation, 1 residual, 2 Jacobian)
-  int trace(const std::vector<int>& L, int sX, int which) {
+  // face traces of slot sX into trL
+  int trace(const std::vector<int>& L, int sX) {
     BatchSet S;
     const int nt = build(S, L, K_TRACE);
     if (!nt) return BSW_OK;
     auto f = [&]<int D, int PP, class TT>() -> int {
-      hipLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sX, which);
+      hipLaunchKernelGGL((kb_trace<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sX);
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
@@ -380,7 +380,7 @@ struct BatchEngine {
   // traces of the linearisation state for all of L; diagonal blocks and their
   // inverses for the instances in B (a subset of L)
   int linearize(const std::vector<int>& L, const std::vector<int>& B) {
-    if (int rc = trace(L, B_W, 0)) return rc;
+    if (int rc = trace(L, B_W)) return rc;
     BatchSet S;
     const int nt = build(S, B, K_E1);
     if (!nt) return BSW_OK;
@@ -507,8 +507,6 @@ struct BatchEngine {
     d.blk = (float*)I->disc->blocks;
     d.blk_raw = (T*)I->disc->blocks_raw;
     d.trL = (T*)I->disc->trL;
-    d.trA = (T*)I->disc->trA;
-    d.trX = (T*)I->disc->trX;
     d.part = I->part;
     d.ntile = I->ntile;
     d.ntile_e = I->ntile_e;

@@ -59,8 +59,6 @@ struct InstDesc {
   float* blk;       // block-Jacobi inverses (FP32), [row][col][n_el]
   T* blk_raw;       // diagonal blocks, [n_el][row][col]
   T* trL;           // face traces of the linearisation state
-  T* trA;           // face traces of the last residual argument
-  T* trX;           // face traces of the last Jacobian argument
   double* part;     // reduction partials, [row][tile]
   int ntile;        // vector tiles: ceil(len / kVT)
   int ntile_e;      // element tiles of 256: ceil(n_el / 256)
@@ -98,16 +96,15 @@ __global__ void __launch_bounds__(256) kb_step_begin(const InstDesc<T>* __restri
   if (e < I.m.n_el) step_begin_elem<D, P, T>(bslot(I, sW, 0), bslot(I, sB, 0), I.m, I.p, e);
 }
 
-// face traces of slot sX into trL (which 0), trA (1) or trX (2); tiles of
-// 256 (field, face, element) items
+// face traces of slot sX (the linearisation state) into trL; tiles of 256
+// (field, face, element) items
 template <int D, int P, class T>
-__global__ void __launch_bounds__(256) kb_trace(const InstDesc<T>* __restrict__ ds, BatchSet A, int sX, int which) {
+__global__ void __launch_bounds__(256) kb_trace(const InstDesc<T>* __restrict__ ds, BatchSet A, int sX) {
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int64_t item = (int64_t)(blockIdx.x - A.tile0[ai]) * 256 + threadIdx.x;
-  T* tr = which == 0 ? I.trL : (which == 1 ? I.trA : I.trX);
   if (item < (int64_t)Shape<D, P>::NF * Shape<D, P>::NFC * I.m.n_el)
-    trace_item<D, P, T>(bslot(I, sX, A.jv[ai]), tr, I.m.n_el, item);
+    trace_item<D, P, T>(bslot(I, sX, A.jv[ai]), I.trL, I.m.n_el, item);
 }
 
 // MODE 0: R = residual(W; b_old); MODE 1: y = J(W) x with the traces of W in

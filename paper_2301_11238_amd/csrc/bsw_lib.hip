@@ -72,8 +72,6 @@ struct bsw_disc_s {
   // face traces (field values at every face point): of the linearisation
   // state, of the last operator argument and of the last Jacobian argument
   void* trL = nullptr;
-  void* trA = nullptr;
-  void* trX = nullptr;
   // reduction scratch
   double* part = nullptr;
   size_t part_len = 0;
@@ -949,8 +947,7 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
   }
   const size_t ntr = (size_t)d->ref.nf * d->ref.nfc * d->ref.nfq * M->n_el * d->wsize;
   int rc = BSW_OK;
-  for (void** t : {&d->trL, &d->trA, &d->trX})
-    if (!rc && hipMalloc(t, ntr) != hipSuccess) rc = fail(c, BSW_E_OOM, "face-trace storage");
+  if (hipMalloc(&d->trL, ntr) != hipSuccess) rc = fail(c, BSW_E_OOM, "face-trace storage");
   if (!rc) rc = dev_alloc(c, &d->red_out, 64);
   if (!rc) rc = dev_alloc(c, &d->hcoef, 80);
   if (!rc && hipMalloc(&d->dirtab, 28 * d->wsize) != hipSuccess) rc = fail(c, BSW_E_OOM, "Dirichlet table");
@@ -966,7 +963,7 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
 int bsw_disc_destroy(bsw_disc d) {
   if (!d) return BSW_OK;
   hfree(d->blocks); hfree(d->blocks_raw); hfree(d->part); hfree(d->red_out);
-  hfree(d->trL); hfree(d->trA); hfree(d->trX);
+  hfree(d->trL);
   if (d->eng) d->eng_free(d->eng);
   hfree(d->gm); hfree(d->hcoef); hfree(d->dirtab);
   if (d->red_host) (void)hipHostFree(d->red_host);
