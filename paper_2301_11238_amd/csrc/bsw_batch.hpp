@@ -260,7 +260,7 @@ struct BatchEngine {
   }
 
   // ------------------------------------------------------------ launch sets
-  enum Kind { K_ETILE, K_E256, K_E1, K_ITEM, K_VEC, K_ONE, K_TRACE };
+  enum Kind { K_ETILE, K_E256, K_E1, K_ITEM, K_VEC, K_ONE, K_TRACE, K_COLS };
   int tiles_of(const BInst<T>* I, int kind) const {
     switch (kind) {
       case K_ETILE: return (int)((I->n_el + eb_cur - 1) / eb_cur);
@@ -269,6 +269,7 @@ struct BatchEngine {
       case K_ITEM: return (int)(BS * ((I->n_el + 255) / 256));  // row tiles (row_tile)
       case K_VEC: return I->ntile;
       case K_TRACE: return (int)((NFNFC * I->n_el + 255) / 256);
+      case K_COLS: return cols_tiles_for(BS, (int)I->n_el);  // jac_columns_elem workgroups
     }
     return 1;
   }
@@ -386,8 +387,9 @@ struct BatchEngine {
     if (!nt) return BSW_OK;
     auto f = [&]<int D, int PP, class TT>() -> int {
       using Sh = Shape<D, PP>;
-      hipLaunchKernelGGL((kb_jac_columns<D, PP, TT>), dim3(nt), dim3(Sh::BS <= 64 ? 64 : 128), 0, c->stream,
-                         d_desc, S, (int)B_W);
+      BatchSet Sc;
+      const int ncol = build(Sc, B, K_COLS);
+      hipLaunchKernelGGL((kb_jac_columns<D, PP, TT>), dim3(ncol), dim3(256), 0, c->stream, d_desc, Sc, (int)B_W);
       HIPCHK(c, hipGetLastError());
       hipLaunchKernelGGL((kb_block_inverse<Sh::BS, TT>), dim3(nt), dim3(inv_threads<Sh::BS>()), 0, c->stream, d_desc,
                          S);

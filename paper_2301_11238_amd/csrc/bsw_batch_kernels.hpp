@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(NT, (elem_waves<D, P, T>())) kb_elem(const Ins
 }
 
 template <int D, int P, class T>
-__global__ void __launch_bounds__(128) kb_jac_columns(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW) {
+__global__ void __launch_bounds__(256) kb_jac_columns(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW) {
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
   jac_columns_elem<D, P, T>(bslot(I, sW, 0), I.trL, I.blk_raw, I.m, I.p, blockIdx.x - A.tile0[ai]);

@@ -687,13 +687,21 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
 // Diagonal block of element e = blockIdx.x, one lane per column, written
 // element-major and row-major: blocks[(e * BS + row) * BS + col] (coalesced
 // across the columns of a row).
+// Diagonal-block columns: one lane per column, the lanes of a 256-thread
+// workgroup packed with the columns of as many whole elements as fit (six at
+// BS = 42, three at BS = 70), so that few lanes idle.
+template <int BS>
+constexpr int cols_epb() { return 256 / BS; }
+constexpr int cols_tiles_for(int bs, int n) { return (n + 256 / bs - 1) / (256 / bs); }
+
 template <int D, int P, class T>
 __device__ __forceinline__ void jac_columns_elem(const T* __restrict__ W, const T* __restrict__ trW,
                                                  T* __restrict__ blocks, const MeshView<T>& m, const DevParams<T>& p,
-                                                 int e) {
+                                                 int g) {
   using S = Shape<D, P>;
-  const int col = threadIdx.x;
-  if (col >= S::BS) return;
+  constexpr int EPB = cols_epb<S::BS>();
+  const int col = threadIdx.x % S::BS, e = g * EPB + (int)threadIdx.x / S::BS;
+  if ((int)threadIdx.x >= EPB * S::BS || e >= m.n_el) return;
   T acc[S::NF][S::NP];
   elem_tangent<D, P, T, true>(tab<D, P, T>(), W, trW, nullptr, nullptr, m, p, e, col, acc);
   T* blk = blocks + (size_t)e * S::BS * S::BS;
@@ -708,7 +716,7 @@ __device__ __forceinline__ void jac_columns_elem(const T* __restrict__ W, const 
 }
 
 template <int D, int P, class T>
-__global__ void __launch_bounds__(128) k_jac_columns(const T* __restrict__ W, const T* __restrict__ trW,
+__global__ void __launch_bounds__(256) k_jac_columns(const T* __restrict__ W, const T* __restrict__ trW,
                                                       T* __restrict__ blocks, MeshView<T> m, DevParams<T> p) {
   jac_columns_elem<D, P, T>(W, trW, blocks, m, p, blockIdx.x);
 }

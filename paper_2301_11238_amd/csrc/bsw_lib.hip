@@ -607,11 +607,11 @@ struct LinearizeLaunch {
     using S = Shape<D, P>;
     auto m = view<T>(d);
     bsw_ctx c = d->mesh->ctx;
-    const int tpb = S::BS <= 64 ? 64 : 128;
     if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
     hipLaunchKernelGGL((k_trace<D, P, T>), grid1((int64_t)S::NF * S::NFC * m.n_el), dim3(256), 0, c->stream,
                        (const T*)d->lin_W, (T*)d->trL, m.n_el);
-    hipLaunchKernelGGL((k_jac_columns<D, P, T>), dim3(m.n_el), dim3(tpb), 0, c->stream, (const T*)d->lin_W,
+    hipLaunchKernelGGL((k_jac_columns<D, P, T>), dim3(cols_tiles_for(S::BS, m.n_el)), dim3(256), 0, c->stream,
+                       (const T*)d->lin_W,
                        (const T*)d->trL, (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt,
                                                                             (const T*)d->dirtab));
     HIPCHK(c, hipGetLastError());
