@@ -596,22 +596,27 @@ __global__ void __launch_bounds__(256, (elem_waves<D, P, T>())) k_elem_blocked(c
                                    xcd_tile(blockIdx.x, gridDim.x) * Blk<D, P>::EB);
 }
 
-// Tangent of the element residual.  The perturbation is either a full vector
-// x (matrix-free Jacobian product: own and neighbour coefficients) or the
-// unit vector of one own degree of freedom (a column of the diagonal block).
-template <int D, int P, class T, bool COLUMN>
-__device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __restrict__ W, const T* __restrict__ trW,
-                                             const T* __restrict__ x, const T* __restrict__ trX,
-                                             const MeshView<T>& m, const DevParams<T>& p, int e, int col,
-                                             T (&acc)[Shape<D, P>::NF][Shape<D, P>::NP]) {
+// Tangent of the element residual along the unit vector of one own degree of
+// freedom, col = f * N_p + i (a column of the diagonal block): the neighbour's
+// side is held fixed.  wl: the element's coefficients (row f * N_p + i), in
+// LDS and shared by the lanes of the element's columns.
+template <int D, int P, class T>
+__device__ __forceinline__ void column_tangent(const Tab<D, P, T>& tb, const T* wl, const T* __restrict__ trW,
+                                               const MeshView<T>& m, const DevParams<T>& p, int e, int col,
+                                               T (&acc)[Shape<D, P>::NF][Shape<D, P>::NP]) {
   using S = Shape<D, P>;
   const int n = m.n_el;
-  T w[S::NF][S::NP];
-  load_coeffs<D, P, T>(W, n, e, w);
-  T v[COLUMN ? 1 : S::NF][COLUMN ? 1 : S::NP];
-  if constexpr (!COLUMN) load_coeffs<D, P, T>(x, n, e, v);
-  const int cf = COLUMN ? col / S::NP : 0;
-  const int ci = COLUMN ? col % S::NP : 0;
+  auto at = [&](const T (&phi)[S::NP], T (&X)[S::NF]) {
+#pragma unroll
+    for (int f = 0; f < S::NF; ++f) {
+      T s = T(0);
+#pragma unroll
+      for (int i = 0; i < S::NP; ++i) s += phi[i] * wl[f * S::NP + i];
+      X[f] = s;
+    }
+  };
+  const int cf = col / S::NP;
+  const int ci = col % S::NP;
   Geo<D, T> g;
   load_geo<D, T>(m, e, g);
 #pragma unroll
@@ -621,13 +626,9 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
 #pragma unroll 1
   for (int q = 0; q < S::NQ; ++q) {
     T X[S::NF], dX[S::NF];
-    interp<D, P, T>(tb.phi[q], w, X);
-    if constexpr (COLUMN) {
+    at(tb.phi[q], X);
 #pragma unroll
-      for (int f = 0; f < S::NF; ++f) dX[f] = (f == cf) ? tb.phi[q][ci] : T(0);
-    } else {
-      interp<D, P, T>(tb.phi[q], v, dX);
-    }
+    for (int f = 0; f < S::NF; ++f) dX[f] = (f == cf) ? tb.phi[q][ci] : T(0);
     Pt<D, T> s, ds;
     unpack<D, T>(X, s);
     unpack<D, T>(dX, ds);
@@ -649,13 +650,9 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
 #pragma unroll 1
     for (int rr = 0; rr < S::NFQ; ++rr) {
       T Xm[S::NF], dXm[S::NF];
-      interp<D, P, T>(tb.fphi[fc][rr], w, Xm);
-      if constexpr (COLUMN) {
+      at(tb.fphi[fc][rr], Xm);
 #pragma unroll
-        for (int f = 0; f < S::NF; ++f) dXm[f] = (f == cf) ? tb.fphi[fc][rr][ci] : T(0);
-      } else {
-        interp<D, P, T>(tb.fphi[fc][rr], v, dXm);
-      }
+      for (int f = 0; f < S::NF; ++f) dXm[f] = (f == cf) ? tb.fphi[fc][rr][ci] : T(0);
       Pt<D, T> sm, sp, dsm, dsp;
       unpack<D, T>(Xm, sm);
       unpack<D, T>(dXm, dsm);
@@ -663,16 +660,10 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
         T Xp[S::NF];
         load_trace<D, P, T>(trW, n, code >> 2, code & 3, S::NFQ - 1 - rr, Xp);
         unpack<D, T>(Xp, sp);
-        if constexpr (COLUMN) {
-          T z[S::NF];
+        T z[S::NF];
 #pragma unroll
-          for (int f = 0; f < S::NF; ++f) z[f] = T(0);
-          unpack<D, T>(z, dsp);
-        } else {
-          T dXp[S::NF];
-          load_trace<D, P, T>(trX, n, code >> 2, code & 3, S::NFQ - 1 - rr, dXp);
-          unpack<D, T>(dXp, dsp);
-        }
+        for (int f = 0; f < S::NF; ++f) z[f] = T(0);
+        unpack<D, T>(z, dsp);
       } else {
         exterior<D, T>(p, nv, -1 - code, sm, sp);
         exterior_tan<D, T>(p, nv, -1 - code, dsm, dsp);
@@ -684,9 +675,6 @@ __device__ __forceinline__ void elem_tangent(const Tab<D, P, T>& tb, const T* __
   }
 }
 
-// Diagonal block of element e = blockIdx.x, one lane per column, written
-// element-major and row-major: blocks[(e * BS + row) * BS + col] (coalesced
-// across the columns of a row).
 // Diagonal-block columns: one lane per column, the lanes of a 256-thread
 // workgroup packed with the columns of as many whole elements as fit (six at
 // BS = 42, three at BS = 70), so that few lanes idle.
@@ -700,10 +688,15 @@ __device__ __forceinline__ void jac_columns_elem(const T* __restrict__ W, const 
                                                  int g) {
   using S = Shape<D, P>;
   constexpr int EPB = cols_epb<S::BS>();
-  const int col = threadIdx.x % S::BS, e = g * EPB + (int)threadIdx.x / S::BS;
-  if ((int)threadIdx.x >= EPB * S::BS || e >= m.n_el) return;
+  const int col = threadIdx.x % S::BS, el = (int)threadIdx.x / S::BS, e = g * EPB + el;
+  const bool live = (int)threadIdx.x < EPB * S::BS && e < m.n_el;
+  // the element's coefficients, once per element in LDS (lane col loads entry col)
+  __shared__ T wl[EPB][S::BS];
+  if (live) wl[el][col] = W[(size_t)col * m.n_el + e];
+  __syncthreads();
+  if (!live) return;
   T acc[S::NF][S::NP];
-  elem_tangent<D, P, T, true>(tab<D, P, T>(), W, trW, nullptr, nullptr, m, p, e, col, acc);
+  column_tangent<D, P, T>(tab<D, P, T>(), wl[el], trW, m, p, e, col, acc);
   T* blk = blocks + (size_t)e * S::BS * S::BS;
 #pragma unroll
   for (int f = 0; f < S::NF; ++f)
