@@ -740,6 +740,26 @@ constexpr int inv_threads() { return 64 * ((BS + 63) / 64); }
 template <int BS, class T>
 constexpr int inv_waves() { return BS > 64 && sizeof(T) == 8 ? 3 : 4; }
 
+// the device library's wave reduction of 64-bit keys (its 32-bit siblings are
+// declared by the HIP headers)
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
+
+// integer keys of non-negative floats (their bit patterns order like the values)
+template <class T> struct PivotKey;
+// (wave_max: the maximum over all 64 lanes of the wave, every lane active)
+template <> struct PivotKey<double> {
+  using U = unsigned long long;
+  static __device__ __forceinline__ U bits(double v) { return (U)__double_as_longlong(v); }
+  static __device__ __forceinline__ double value(U k) { return __longlong_as_double((long long)k); }
+  static __device__ __forceinline__ U wave_max(U k) { return __ockl_wfred_max_u64(k); }
+};
+template <> struct PivotKey<float> {
+  using U = unsigned int;
+  static __device__ __forceinline__ U bits(float v) { return (U)__float_as_uint(v); }
+  static __device__ __forceinline__ float value(U k) { return __uint_as_float(k); }
+  static __device__ __forceinline__ U wave_max(U k) { return __ockl_wfred_max_u32(k); }
+};
+
 // the value v holds in lane l of the wave (l wave-uniform), as a scalar
 __device__ __forceinline__ float lane_value(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -772,17 +792,18 @@ __device__ __forceinline__ void block_inverse_elem(const T* __restrict__ A, floa
   T dp = T(1);  // the lane's own pivot value
   for (int k = 0; k < BS; ++k) {
     const int buf = k & 1;
-    // a NaN entry counts as the largest, so the pivot is always a row not yet
-    // used (every row is used exactly once and piv[] stays a permutation)
-    T best = used ? T(-1) : fabs(r[0]);
-    if (best != best) best = T(INFINITY);
-    int bi = t;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const T ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
+    // the wave's pivot candidate: largest |entry| among its rows not yet used,
+    // lowest row on ties, as two wave reductions on an integer key (the bits
+    // of a non-negative float order like its value; used rows key 0).  A NaN
+    // entry counts as the largest, so the pivot is always a row not yet used
+    // (every row is used exactly once and piv[] stays a permutation).
+    T av = fabs(r[0]);
+    if (av != av) av = T(INFINITY);
+    using K = typename PivotKey<T>::U;
+    const K key = used ? K(0) : PivotKey<T>::bits(av) + K(1);
+    const K mx = PivotKey<T>::wave_max(key);
+    int bi = (int)__ockl_wfred_min_u32(key == mx ? (unsigned)t : 0xffffffffu);
+    T best = mx == K(0) ? T(-1) : PivotKey<T>::value(mx - K(1));
     if constexpr (NW == 1) {
       // one wave: the pivot row is read from the pivot lane's registers into
       // scalar registers (no LDS traffic and no barrier per step)
