@@ -232,11 +232,33 @@ __global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict_
 // the vector itself and no pass only rescales.
 
 
+// the device library's wave sum of doubles (the 32-bit reductions are
+// declared by the HIP headers)
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
+
+// red[u][tid] holds the 256 products of rows r0 + u (u < 8) of one tile:
+// wave w sums rows 2w and 2w + 1, each lane four consecutive products, then
+// one wave reduction (a fixed order); the row sums below nrow go to the
+// tile's partials.  Called by all 256 threads, between barriers.
+__device__ __forceinline__ void fold_group(const double (&red)[8][257], int r0, int nrow, double* __restrict__ part,
+                                           int ntile, int t) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int u = 2 * wv + h;
+    double s = red[u][lane * 4];
+#pragma unroll
+    for (int m = 1; m < 4; ++m) s += red[u][lane * 4 + m];
+    s = __ockl_wfred_add_f64(s);
+    if (lane == 0 && r0 + u < nrow) part[(int64_t)(r0 + u) * ntile + t] = s;
+  }
+}
+
 // per-tile partials of rows r: V_r . w (r < rows, or r < rows - 1 and the last
 // row w . w when self).  Eight rows at a time: every lane forms its two-term
 // products (sixteen independent loads in flight), the 8 x 256 products are
-// transposed through LDS, 32 lanes per row add eight each and a 32-lane
-// butterfly finishes the row -- a fixed summation order.
+// transposed through LDS and fold_group sums each row -- a fixed summation
+// order.
 template <class T>
 __device__ __forceinline__ void tile_dots(const InstDesc<T>& I, const T* __restrict__ V, double w0, double w1,
                                           int64_t i0, int rows, int self, int t) {
@@ -244,7 +266,7 @@ __device__ __forceinline__ void tile_dots(const InstDesc<T>& I, const T* __restr
   const int64_t i1 = i0 + 256;
   const int nv = self ? rows - 1 : rows;  // rows against stored vectors
   const bool in0 = i0 < I.len, in1 = i1 < I.len;
-  const int tid = threadIdx.x, ru = tid >> 5, rl = tid & 31;
+  const int tid = threadIdx.x;
   for (int r0 = 0; r0 < rows; r0 += 8) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -259,12 +281,7 @@ __device__ __forceinline__ void tile_dots(const InstDesc<T>& I, const T* __restr
       red[u][tid] = a;
     }
     __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) s += red[ru][rl * 8 + m];
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (rl == 0 && r0 + ru < rows) I.part[(int64_t)(r0 + ru) * I.ntile + t] = s;
+    fold_group(red, r0, rows, I.part, I.ntile, t);
     __syncthreads();
   }
 }
@@ -319,7 +336,7 @@ __global__ void __launch_bounds__(256) kb_dots_cached(const InstDesc<T>* __restr
   }
   const double w0 = in0 ? (double)w[i0] : 0.0, w1 = in1 ? (double)w[i1] : 0.0;
   __shared__ double red[8][257];
-  const int tid = threadIdx.x, ru = tid >> 5, rl = tid & 31;
+  const int tid = threadIdx.x;
 #pragma unroll
   for (int r0 = 0; r0 < kRowsCached + 8; r0 += 8) {
     if (r0 < rows) {
@@ -333,12 +350,7 @@ __global__ void __launch_bounds__(256) kb_dots_cached(const InstDesc<T>* __restr
         red[u][tid] = a;
       }
       __syncthreads();
-      double s = 0.0;
-#pragma unroll
-      for (int m = 0; m < 8; ++m) s += red[ru][rl * 8 + m];
-#pragma unroll
-      for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off);
-      if (rl == 0 && r0 + ru < rows) I.part[(int64_t)(r0 + ru) * I.ntile + t] = s;
+      fold_group(red, r0, rows, I.part, I.ntile, t);
       __syncthreads();
     }
   }
@@ -384,7 +396,7 @@ __global__ void __launch_bounds__(256) kb_axpy_dots_cached(const InstDesc<T>* __
   const double w0 = in0 ? a0 : 0.0, w1 = in1 ? a1 : 0.0;
   // partials of V_r . t (r < rows), as tile_dots
   __shared__ double red[8][257];
-  const int tid = threadIdx.x, ru = tid >> 5, rl = tid & 31;
+  const int tid = threadIdx.x;
   const int nrow = rows;
 #pragma unroll
   for (int r0 = 0; r0 < kRowsCached; r0 += 8) {
@@ -397,12 +409,7 @@ __global__ void __launch_bounds__(256) kb_axpy_dots_cached(const InstDesc<T>* __
         red[u][tid] = a;
       }
       __syncthreads();
-      double s2 = 0.0;
-#pragma unroll
-      for (int m = 0; m < 8; ++m) s2 += red[ru][rl * 8 + m];
-#pragma unroll
-      for (int off = 16; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
-      if (rl == 0 && r0 + ru < nrow) I.part[(int64_t)(r0 + ru) * I.ntile + t] = s2;
+      fold_group(red, r0, nrow, I.part, I.ntile, t);
       __syncthreads();
     }
   }
