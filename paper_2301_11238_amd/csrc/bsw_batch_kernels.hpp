@@ -69,19 +69,23 @@ __device__ __forceinline__ T* bslot(const InstDesc<T>& I, int s, int j) {
   return I.ws + (int64_t)((s & 0xffff) + ((s & kSlotJ) ? j : 0)) * I.ld;
 }
 
-// 256-lane tree sum / max / min; the result is valid on lane 0
+// the device library's wave reductions of doubles (its 32-bit reductions are
+// declared by the HIP headers)
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_max_f64(double);
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_min_f64(double);
+
+// 256-lane sum / max / min (a wave reduction per wave, then the four wave
+// results in wave order: a fixed order); the result is valid on every lane.
+// Called by all 256 threads with every lane active.
 __device__ __forceinline__ double bred(double v, int op) {
-  __shared__ double sh[256];
-  sh[threadIdx.x] = v;
+  __shared__ double sh[4];
+  const double w = op == 0 ? __ockl_wfred_add_f64(v) : (op == 1 ? __ockl_wfred_max_f64(v) : __ockl_wfred_min_f64(v));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      const double a = sh[threadIdx.x], b = sh[threadIdx.x + s];
-      sh[threadIdx.x] = op == 0 ? a + b : (op == 1 ? fmax(a, b) : fmin(a, b));
-    }
-    __syncthreads();
-  }
-  const double r = sh[0];
+  double r = sh[0];
+#pragma unroll
+  for (int k = 1; k < 4; ++k) r = op == 0 ? r + sh[k] : (op == 1 ? fmax(r, sh[k]) : fmin(r, sh[k]));
   __syncthreads();
   return r;
 }
@@ -231,10 +235,6 @@ __global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict_
 // sigma_r = sc[kScS + r], so each new vector's norm is computed exactly from
 // the vector itself and no pass only rescales.
 
-
-// the device library's wave sum of doubles (the 32-bit reductions are
-// declared by the HIP headers)
-extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
 
 // red[u][tid] holds the 256 products of rows r0 + u (u < 8) of one tile:
 // wave w sums rows 2w and 2w + 1, each lane four consecutive products, then
