@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(NT, (elem_waves<D, P, T>())) kb_elem(const Ins
   const int e0 = (b - A.tile0[ai]) * Blk<D, P, NT>::EB;
   elem_blocked_tile<D, P, T, MODE, NT>(bslot(I, sW, j), MODE == 1 ? bslot(I, sX, j) : nullptr,
                                    MODE == 0 ? bslot(I, sB, j) : nullptr, bslot(I, sOut, j),
-                                   MODE == 0 ? nullptr : I.trL, nullptr, I.m, I.p, e0);
+                                   MODE == 0 ? nullptr : I.trL, I.m, I.p, e0);
 }
 
 template <int D, int P, class T>

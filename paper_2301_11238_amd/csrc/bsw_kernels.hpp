@@ -422,16 +422,15 @@ struct Blk {
   static constexpr int NFF = 1 + D + D * D;                            // reals per face point
 };
 
-// MODE 0: residual (x unused, bold subtracted; trW, trX unused: the
-// neighbours' side of W is evaluated here); MODE 1: Jacobian product along x
-// (bold and trX unused; the neighbours' side of W from the linearisation's
-// traces trW, that of x evaluated here).  One tile: elements e0 .. e0+EB-1
-// of one mesh.
+// MODE 0: residual (x unused, bold subtracted; trW unused: the neighbours'
+// side of W is evaluated here); MODE 1: Jacobian product along x (bold
+// unused; the neighbours' side of W from the linearisation's traces trW, that
+// of x evaluated here).  One tile: elements e0 .. e0+EB-1 of one mesh.
 template <int D, int P, class T, int MODE, int NT = 256>
 __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const T* __restrict__ x,
                                                   const T* __restrict__ bold, T* __restrict__ out,
-                                                  const T* __restrict__ trW, const T* __restrict__ trX,
-                                                  const MeshView<T>& m, const DevParams<T>& p, int e0) {
+                                                  const T* __restrict__ trW, const MeshView<T>& m,
+                                                  const DevParams<T>& p, int e0) {
   using S = Shape<D, P>;
   using B = Blk<D, P, NT>;
   constexpr bool TAN = MODE == 1;
@@ -590,9 +589,8 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
 template <int D, int P, class T, int MODE>
 __global__ void __launch_bounds__(256, (elem_waves<D, P, T>())) k_elem_blocked(const T* __restrict__ W, const T* __restrict__ x,
                                                        const T* __restrict__ bold, T* __restrict__ out,
-                                                       const T* __restrict__ trW, const T* __restrict__ trX,
-                                                       MeshView<T> m, DevParams<T> p) {
-  elem_blocked_tile<D, P, T, MODE>(W, x, bold, out, trW, trX, m, p,
+                                                       const T* __restrict__ trW, MeshView<T> m, DevParams<T> p) {
+  elem_blocked_tile<D, P, T, MODE>(W, x, bold, out, trW, m, p,
                                    xcd_tile(blockIdx.x, gridDim.x) * Blk<D, P>::EB);
 }
 

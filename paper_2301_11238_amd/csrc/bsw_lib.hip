@@ -561,7 +561,7 @@ struct OpLaunch {
     if (int rc = sync_dirtab<T>(d, *p)) return rc;
     // one element pass: it evaluates the neighbours' side of W itself
     hipLaunchKernelGGL((k_elem_blocked<D, P, T, 0>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0, st, (const T*)W,
-                       (const T*)nullptr, (const T*)bold, (T*)R, (const T*)nullptr, (const T*)nullptr, m,
+                       (const T*)nullptr, (const T*)bold, (T*)R, (const T*)nullptr, m,
                        devparams<T>(*p, dt, (const T*)d->dirtab));
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
@@ -594,7 +594,7 @@ struct JacApplyLaunch {
     if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
     const auto prm = devparams<T>(d->lin_prm, d->lin_dt, (const T*)d->dirtab);
     hipExtLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), ge, dim3(256), 0, st, ev_start, ev_stop, 0,
-                          (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, tL, (const T*)nullptr, m, prm);
+                          (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, tL, m, prm);
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
