@@ -30,7 +30,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
 # scaled by the same counters on a plain copy of known size; None until the
 # counters are taken on the current kernel.
-TRAFFIC_BYTES = {"jacobian_apply": 14614528.0}  # element pass; counter summary under profiles/
+TRAFFIC_BYTES = {"jacobian_apply": 14612480.0}  # element pass; counter summary under profiles/
 
 
 def parse():
