@@ -422,8 +422,8 @@ def serving(ctx, n_req, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path is built "
+              f"and measured on one GPU; its sharding is a design note, not code)", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as wl
