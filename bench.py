@@ -539,7 +539,7 @@ def main():
                    "gmres_per_step": st["gmres_total"] / max(1, st["steps"]),
                    "capped_steps": st["capped"],
                    "applies_per_step": applies / max(1, st["steps"]),
-                   # per pipelined Arnoldi step (eight launches): host time to issue it and
+                   # per pipelined Arnoldi step (seven launches): host time to issue it and
                    # host time blocked on its results; issue < step time means the launch
                    # path is not the limit (the device is)
                    "arnoldi_step_us": 1e6 * el / max(1.0, st["arnoldi_steps"]) if st["arnoldi_steps"] else None,

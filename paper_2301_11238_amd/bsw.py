@@ -136,6 +136,25 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def check_tensor(t, device: int, dtype, min_numel: int, name: str = "tensor"):
+    """Refuses, before any library call, a device argument the kernels would
+    read or write out of bounds: it must be a contiguous CUDA tensor on the
+    context's device, of the discretisation's dtype, with at least min_numel
+    elements.  Returns its pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name}: must be on cuda:{device}, is on {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, the discretisation needs {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {min_numel} needed")
+    return _ptr(t)
+
+
 def make_params(p, bc: int = 1, dirichlet=None, dirichlet_tags=None) -> Params:
     q = Params()
     for k in ("g", "rho", "alpha", "eta", "sigma0", "gamma", "beta"):
@@ -295,6 +314,14 @@ class Disc:
     def _ck(self, rc):
         return self.ctx._check(rc, self.ctx.h)
 
+    def _state(self, t, name="W"):
+        """Pointer of a full state-sized device argument (n_f N_p n_el reals)."""
+        return check_tensor(t, self.ctx.device, self.dtype, self.nf * self.np * self.n_el, name)
+
+    def _rows(self, t, nfields, name):
+        """Pointer of a device argument of nfields fields ([nfields][N_p][n_el])."""
+        return check_tensor(t, self.ctx.device, self.dtype, nfields * self.np * self.n_el, name)
+
     def empty(self, nfields=None):
         import torch
         nf = self.nf if nfields is None else nfields
@@ -309,13 +336,13 @@ class Disc:
 
     def project_ic(self, ic, W=None):
         W = self.empty() if W is None else W
-        self._ck(lib().bsw_project_ic(self.h, C.byref(make_ic(ic)), _ptr(W)))
+        self._ck(lib().bsw_project_ic(self.h, C.byref(make_ic(ic)), self._state(W)))
         return W
 
     def bed_interpolate(self, bed, H=None):
         """Order-m0 interpolant of an analytic bed, [N_p, n_el] on the device."""
         H = self.empty(1) if H is None else H
-        self._ck(lib().bsw_bed_interpolate(self.h, C.byref(make_bed(bed)), _ptr(H)))
+        self._ck(lib().bsw_bed_interpolate(self.h, C.byref(make_bed(bed)), self._rows(H, 1, "H")))
         return H[0] if H.dim() == 3 else H
 
     def set_orders(self, m1: int, m2: int, m3: int):
@@ -325,63 +352,65 @@ class Disc:
     def set_bed(self, H):
         """Bed coefficients [N_p, n_el] (device tensor kept by reference), or None."""
         self._bed = H
-        self._ck(lib().bsw_disc_set_bed(self.h, _ptr(H) if H is not None else None))
+        self._ck(lib().bsw_disc_set_bed(self.h, self._rows(H, 1, "H") if H is not None else None))
 
     def step_begin(self, params: Params, dt: float, W_old, b_old=None):
         b_old = self.empty(1 + self.dim) if b_old is None else b_old
-        self._ck(lib().bsw_step_begin(self.h, C.byref(params), float(dt), _ptr(W_old), _ptr(b_old)))
+        self._ck(lib().bsw_step_begin(self.h, C.byref(params), float(dt), self._state(W_old, "W_old"),
+                                    self._rows(b_old, 1 + self.dim, "b_old")))
         return b_old
 
     def operator_apply(self, params: Params, dt: float, W, b_old, R=None):
         R = self.empty() if R is None else R
-        self._ck(lib().bsw_operator_apply(self.h, C.byref(params), float(dt), _ptr(W), _ptr(b_old), _ptr(R)))
+        self._ck(lib().bsw_operator_apply(self.h, C.byref(params), float(dt), self._state(W),
+                                         self._rows(b_old, 1 + self.dim, "b_old"), self._state(R, "R")))
         return R
 
     def jacobian_linearize(self, params: Params, dt: float, W):
         self._lin_W = W  # the library keeps a reference to W's memory
-        self._ck(lib().bsw_jacobian_linearize(self.h, C.byref(params), float(dt), _ptr(W)))
+        self._ck(lib().bsw_jacobian_linearize(self.h, C.byref(params), float(dt), self._state(W)))
 
     def jacobian_apply(self, x, y=None):
         y = self.empty() if y is None else y
-        self._ck(lib().bsw_jacobian_apply(self.h, _ptr(x), _ptr(y)))
+        self._ck(lib().bsw_jacobian_apply(self.h, self._state(x, "x"), self._state(y, "y")))
         return y
 
     def precond_apply(self, x, y=None):
         y = self.empty() if y is None else y
-        self._ck(lib().bsw_precond_apply(self.h, _ptr(x), _ptr(y)))
+        self._ck(lib().bsw_precond_apply(self.h, self._state(x, "x"), self._state(y, "y")))
         return y
 
     def jacobian_blocks(self):
         import torch
         bs = self.nf * self.np
         out = torch.empty((self.n_el, bs, bs), dtype=self.dtype, device=self.ctx.torch_device)
-        self._ck(lib().bsw_jacobian_blocks(self.h, _ptr(out)))
+        self._ck(lib().bsw_jacobian_blocks(self.h, check_tensor(out, self.ctx.device, self.dtype, self.n_el * bs * bs, "blocks")))
         return out
 
     def stage_update(self, params, W, dW, alpha: float = 1.0):
         out = (C.c_double * 4)()
-        self._ck(lib().bsw_stage_update(self.h, C.byref(params) if params is not None else None, _ptr(W),
-                                        _ptr(dW), float(alpha), out))
+        self._ck(lib().bsw_stage_update(self.h, C.byref(params) if params is not None else None, self._state(W),
+                                        self._state(dW, "dW"), float(alpha), out))
         return list(out)
 
     def diagnostics(self, params, W):
         out = (C.c_double * 4)()
-        self._ck(lib().bsw_diagnostics(self.h, C.byref(params), _ptr(W), out))
+        self._ck(lib().bsw_diagnostics(self.h, C.byref(params), self._state(W), out))
         return dict(mass=out[0], active_pct=out[1], lambda_max=out[2], h_min=out[3])
 
     def norm2(self, x) -> float:
         out = C.c_double(0.0)
-        self._ck(lib().bsw_norm2(self.h, _ptr(x), C.byref(out)))
+        self._ck(lib().bsw_norm2(self.h, self._state(x, "x"), C.byref(out)))
         return out.value
 
     def cfl_dt(self, params: Params, W, cfl: float) -> float:
         out = C.c_double(0.0)
-        self._ck(lib().bsw_cfl_dt(self.h, C.byref(params), _ptr(W), float(cfl), C.byref(out)))
+        self._ck(lib().bsw_cfl_dt(self.h, C.byref(params), self._state(W), float(cfl), C.byref(out)))
         return out.value
 
     def solve(self, params: Params, opts: Options, W):
         st = SolveStats()
-        rc = lib().bsw_solve(self.h, C.byref(params), C.byref(opts.c()), _ptr(W), C.byref(st))
+        rc = lib().bsw_solve(self.h, C.byref(params), C.byref(opts.c()), self._state(W), C.byref(st))
         self._ck(rc)
         return {k: getattr(st, k) for k, _ in SolveStats._fields_}
 

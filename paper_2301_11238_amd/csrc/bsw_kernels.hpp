@@ -1,8 +1,8 @@
 // HIP kernels of the DG operator, its tangent, the element-block Jacobian and
-// the reductions.  One lane per element: the state is stored SoA with the
-// element index fastest, so every coefficient load of a wavefront is one
-// coalesced 64-element row; the reference tables sit in constant memory and
-// are read as wave-uniform scalars.
+// the reductions.  The state is stored SoA with the element index fastest, so
+// the coefficient loads of consecutive elements coalesce.  The reference
+// tables sit in constant memory; where the lanes of a wave read different
+// entries (different points or modes) those reads take the vector memory path.
 #pragma once
 #include "bsw_device.hpp"
 

@@ -69,8 +69,7 @@ struct bsw_disc_s {
   double lin_dt = 0.0;
   void* blocks = nullptr;      // block inverses (FP32), [row][col][n_el]
   void* blocks_raw = nullptr;  // unfactored blocks, [n_el][row][col]
-  // face traces (field values at every face point): of the linearisation
-  // state, of the last operator argument and of the last Jacobian argument
+  // face traces (field values at every face point) of the linearisation state
   void* trL = nullptr;
   // reduction scratch
   double* part = nullptr;
@@ -81,7 +80,6 @@ struct bsw_disc_s {
   // solver workspace
   void* gm = nullptr;             // whole-solve workspace (state and Krylov vectors)
   size_t gm_bytes = 0;
-  double* hcoef = nullptr;        // device [65]
   void* eng = nullptr;            // whole-solve engine (one-instance batch), type-erased
   void (*eng_free)(void*) = nullptr;
 };
@@ -277,59 +275,6 @@ __global__ void __launch_bounds__(kRedThreads) k_multidot(const T* __restrict__ 
   if (threadIdx.x == 0) part[(size_t)j * gridDim.x + blockIdx.x] = sh[0];
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_sum_rows(const double* __restrict__ part, int nblk, double* out) {
-  const int j = blockIdx.x;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += kRedThreads) acc += part[(size_t)j * nblk + i];
-  __shared__ double sh[kRedThreads];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[j] = sh[0];
-}
-
-// w += sgn * sum_j h[j] V[j] (coefficients passed by value)
-struct Coef {
-  double h[65];
-};
-template <class T>
-__global__ void __launch_bounds__(256) k_multi_axpy(T* __restrict__ w, const T* __restrict__ V, size_t ld, int k,
-                                                     Coef h, double sgn, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int j = 0; j < k; ++j) s += h.h[j] * (double)V[(size_t)j * ld + i];
-  w[i] = (T)((double)w[i] + sgn * s);
-}
-
-// y = s * (w - sum_j h[j] V[j])
-template <class T>
-__global__ void __launch_bounds__(256) k_axpy_scale(const T* __restrict__ w, const T* __restrict__ V, size_t ld, int k,
-                                                     Coef h, double s, T* __restrict__ y, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double acc = (double)w[i];
-  for (int j = 0; j < k; ++j) acc -= h.h[j] * (double)V[(size_t)j * ld + i];
-  y[i] = (T)(acc * s);
-}
-
-template <class T>
-__global__ void __launch_bounds__(256) k_scale_copy(const T* __restrict__ x, T* __restrict__ y, double s, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (T)((double)x[i] * s);
-}
-
-// y = a x + b z
-template <class T>
-__global__ void __launch_bounds__(256) k_axpby(T* __restrict__ y, double a, const T* __restrict__ x, double b,
-                                                const T* __restrict__ z, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (T)(a * (double)x[i] + b * (double)z[i]);
-}
-
 // W += alpha dW with max|alpha dW| and max|W| partials
 template <class T>
 __global__ void __launch_bounds__(kRedThreads) k_axpy_norms(T* __restrict__ W, const T* __restrict__ dW, double alpha,
@@ -344,15 +289,6 @@ __global__ void __launch_bounds__(kRedThreads) k_axpy_norms(T* __restrict__ W, c
     v[1] = fmax(v[1], fabs((double)wn));
   }
   block_reduce<2>(v, ops, part);
-}
-
-template <class T>
-__global__ void __launch_bounds__(kRedThreads) k_absmax(const T* __restrict__ x, int64_t n, double* part) {
-  double v[1] = {0.0};
-  const int ops[1] = {1};
-  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
-    v[0] = fmax(v[0], fabs((double)x[i]));
-  block_reduce<1>(v, ops, part);
 }
 
 // mass, active area, max(|u| + sqrt(g h)), min h over volume points (Sec. 6)
@@ -949,7 +885,6 @@ int bsw_disc_create(bsw_mesh M, int P, int precision, bsw_disc* out) {
   int rc = BSW_OK;
   if (hipMalloc(&d->trL, ntr) != hipSuccess) rc = fail(c, BSW_E_OOM, "face-trace storage");
   if (!rc) rc = dev_alloc(c, &d->red_out, 64);
-  if (!rc) rc = dev_alloc(c, &d->hcoef, 80);
   if (!rc && hipMalloc(&d->dirtab, 28 * d->wsize) != hipSuccess) rc = fail(c, BSW_E_OOM, "Dirichlet table");
   if (!rc && hipHostMalloc((void**)&d->red_host, 80 * sizeof(double), hipHostMallocMapped) != hipSuccess)
     rc = fail(c, BSW_E_OOM, "hipHostMalloc");
@@ -965,7 +900,7 @@ int bsw_disc_destroy(bsw_disc d) {
   hfree(d->blocks); hfree(d->blocks_raw); hfree(d->part); hfree(d->red_out);
   hfree(d->trL);
   if (d->eng) d->eng_free(d->eng);
-  hfree(d->gm); hfree(d->hcoef); hfree(d->dirtab);
+  hfree(d->gm); hfree(d->dirtab);
   if (d->red_host) (void)hipHostFree(d->red_host);
   delete d;
   return BSW_OK;
