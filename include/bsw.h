@@ -156,7 +156,9 @@ typedef struct {
 
 /* ---------------------------------------------------------------- context */
 /* Binds a device and a HIP stream (NULL: the null stream; the caller may pass
- * torch's current stream).  The stream must outlive the context. */
+ * torch's current stream).  The stream must outlive the context.  The first
+ * context on a device also looks up that device's copy of the library's
+ * fixed scratch array (used by bsw_stage_update_noalloc). */
 int bsw_ctx_create(int device, void* hip_stream, bsw_ctx* out);
 int bsw_ctx_destroy(bsw_ctx ctx);
 const char* bsw_last_error(bsw_ctx ctx);
@@ -273,6 +275,21 @@ int bsw_jacobian_blocks(bsw_disc disc, void* blocks);
  * (Sec. 6) with s the shear rate of the 2-D reading (|E| in 1-D). */
 int bsw_stage_update(bsw_disc disc, const bsw_params* prm, void* W, const void* dW,
                      double alpha, double* norms_out);
+/* bsw_stage_update without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, same results as bsw_stage_update, but its
+ * reduction partials and final values live in a fixed per-device array of the
+ * library (4096 partial sums and 64 results, 33 KB per device, held until the
+ * process ends) instead of memory bsw_stage_update allocates on first use.
+ * No hipMalloc, hipFree or allocating library routine is called.  Every
+ * workgroup writes its own partial before the final pass reads it, so nothing
+ * needs clearing between calls.  All calls on one device share the array:
+ * calls that overlap on one GPU (other streams or threads) race, so the
+ * caller serialises them.  BSW_E_ARG if the reduction would need more partial
+ * sums than the array holds (the workgroup counts are capped at 1024, so no
+ * valid discretisation does); BSW_E_STATE for a context without the array. */
+int bsw_stage_update_noalloc(bsw_disc disc, const bsw_params* prm, void* W, const void* dW,
+                             double alpha, double* norms_out);
 /* out4 (host) = {mass, active%, max(|u| + sqrt(g h)), min h} over volume points. */
 int bsw_diagnostics(bsw_disc disc, const bsw_params* prm, const void* W, double* out4);
 /* *out (host) = sqrt(sum x^2) accumulated in FP64. */

@@ -97,6 +97,7 @@ SIGNATURES = {
     "bsw_precond_apply": (C.c_int, [_VP, _VP, _VP]),
     "bsw_jacobian_blocks": (C.c_int, [_VP, _VP]),
     "bsw_stage_update": (C.c_int, [_VP, C.POINTER(Params), _VP, _VP, C.c_double, _DP]),
+    "bsw_stage_update_noalloc": (C.c_int, [_VP, C.POINTER(Params), _VP, _VP, C.c_double, _DP]),
     "bsw_diagnostics": (C.c_int, [_VP, C.POINTER(Params), _VP, _DP]),
     "bsw_norm2": (C.c_int, [_VP, _VP, _DP]),
     "bsw_cfl_dt": (C.c_int, [_VP, C.POINTER(Params), _VP, C.c_double, _DP]),
@@ -391,6 +392,14 @@ class Disc:
         out = (C.c_double * 4)()
         self._ck(lib().bsw_stage_update(self.h, C.byref(params) if params is not None else None, self._state(W),
                                         self._state(dW, "dW"), float(alpha), out))
+        return list(out)
+
+    def stage_update_noalloc(self, params, W, dW, alpha: float = 1.0):
+        """bsw_stage_update_noalloc: the same update and norms, with the
+        library's fixed scratch array instead of allocated partials."""
+        out = (C.c_double * 4)()
+        self._ck(lib().bsw_stage_update_noalloc(self.h, C.byref(params) if params is not None else None,
+                                                self._state(W), self._state(dW, "dW"), float(alpha), out))
         return list(out)
 
     def diagnostics(self, params, W):

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -21,6 +22,18 @@ namespace bsw {
 __constant__ __align__(16) unsigned char c_tables[kTabBytesTotal];
 }
 
+// Reduction scratch of the entry points that allocate nothing
+// (bsw_stage_update_noalloc): up to kScratchPartials per-workgroup partial
+// sums and kScratchOut final values.  Each device the library runs on holds
+// one copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the device (bsw_ctx_s::scratch).
+constexpr int kScratchPartials = 4 * 1024;
+constexpr int kScratchOut = 64;
+static __device__ __align__(256) double scratch[kScratchPartials + kScratchOut];
+constexpr int kMaxScratchDevices = 64;
+static double* g_scratch_dev[kMaxScratchDevices] = {};  // per device: its scratch address
+static std::mutex g_scratch_mu;
+
 using namespace bsw;
 
 // ====================================================================== handles
@@ -29,6 +42,7 @@ struct bsw_ctx_s {
   hipStream_t stream = nullptr;
   std::string err;
   bool tables_staged[2][kNumCombos] = {};
+  double* scratch = nullptr;  // this device's copy of the file-scope scratch array
 };
 
 template <class T>
@@ -475,16 +489,22 @@ int ensure_part(bsw_disc d, size_t len) {
 
 int red_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + kRedThreads - 1) / kRedThreads)); }
 
-// finish a partial reduction of nv values into host out[]
-int finish(bsw_disc d, int nblk, int nv, const int* ops, double* host_out) {
+// finish a partial reduction of nv values (partials part[v * nblk + b]) into
+// the device values dev_out[0..nv) and host out[]
+int finish_into(bsw_disc d, const double* part, double* dev_out, int nblk, int nv, const int* ops,
+                double* host_out) {
   bsw_ctx c = d->mesh->ctx;
-  hipLaunchKernelGGL(k_reduce_final, dim3(nv), dim3(kRedThreads), 0, c->stream, d->part, nblk, nullptr, ops[0],
-                     nv > 1 ? ops[1] : 0, nv > 2 ? ops[2] : 0, nv > 3 ? ops[3] : 0, d->red_out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(nv), dim3(kRedThreads), 0, c->stream, part, nblk, nullptr, ops[0],
+                     nv > 1 ? ops[1] : 0, nv > 2 ? ops[2] : 0, nv > 3 ? ops[3] : 0, dev_out);
   HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipMemcpyAsync(d->red_host, d->red_out, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d->red_host, dev_out, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int k = 0; k < nv; ++k) host_out[k] = d->red_host[k];
   return BSW_OK;
+}
+
+int finish(bsw_disc d, int nblk, int nv, const int* ops, double* host_out) {
+  return finish_into(d, d->part, d->red_out, nblk, nv, ops, host_out);
 }
 
 // --------------------------------------------------------------- kernel launchers
@@ -572,13 +592,13 @@ struct PrecLaunch {
 };
 
 struct DiagLaunch {
-  bsw_disc d; const bsw_params* p; const void* W; int nblk;
+  bsw_disc d; const bsw_params* p; const void* W; int nblk; double* part;
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
     const double thr = p->sigma0 / p->gamma;
     hipLaunchKernelGGL((k_diag<D, P, T>), dim3(nblk), dim3(kRedThreads), 0, d->mesh->ctx->stream, (const T*)W, m,
-                       p->g, thr, d->part);
+                       p->g, thr, part);
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -710,6 +730,26 @@ int bsw_ctx_create(int device, void* hip_stream, bsw_ctx* out) {
   bsw_ctx c = new bsw_ctx_s();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  // this device's copy of the scratch array, looked up once per device with
+  // the device current (the array's name is a host-side stand-in; kernels and
+  // copies must use this address)
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device >= kMaxScratchDevices) {
+      delete c;
+      return fail(nullptr, BSW_E_ARG, "device index beyond the scratch table");
+    }
+    if (!g_scratch_dev[device]) {
+      void* sp = nullptr;
+      const hipError_t se = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+      if (se != hipSuccess || !sp) {
+        delete c;
+        return fail(nullptr, BSW_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(se));
+      }
+      g_scratch_dev[device] = (double*)sp;
+    }
+    c->scratch = g_scratch_dev[device];
+  }
   *out = c;
   return BSW_OK;
 }
@@ -1066,11 +1106,50 @@ int bsw_stage_update(bsw_disc d, const bsw_params* p, void* W, const void* dW, d
   return BSW_OK;
 }
 
+int bsw_stage_update_noalloc(bsw_disc d, const bsw_params* p, void* W, const void* dW, double alpha,
+                             double* norms_out) {
+  if (!d || !W || !dW) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
+  bsw_ctx c = d->mesh->ctx;
+  if (!c->scratch) return fail(c, BSW_E_STATE, "context has no scratch address");
+  const int64_t n = bsw_state_len(d);
+  const int nblk = red_blocks(n);
+  const int nblk_diag = red_blocks(d->mesh->n_el);
+  // partial slots this call needs: 2 per workgroup of the update, 4 per
+  // workgroup of the diagnostics (the workgroup counts are capped at 1024)
+  if ((int64_t)nblk * 2 > kScratchPartials || (int64_t)nblk_diag * 4 > kScratchPartials)
+    return fail(c, BSW_E_ARG, "stage_update_noalloc: the reduction needs more than the " +
+                                  std::to_string(kScratchPartials) + " partial sums of its scratch");
+  double* part = c->scratch;
+  double* dev_out = c->scratch + kScratchPartials;
+  if (d->precision == BSW_FP64)
+    hipLaunchKernelGGL((k_axpy_norms<double>), dim3(nblk), dim3(kRedThreads), 0, c->stream, (double*)W,
+                       (const double*)dW, alpha, n, part);
+  else
+    hipLaunchKernelGGL((k_axpy_norms<float>), dim3(nblk), dim3(kRedThreads), 0, c->stream, (float*)W,
+                       (const float*)dW, alpha, n, part);
+  HIPCHK(c, hipGetLastError());
+  if (!norms_out) return BSW_OK;
+  const int ops2[2] = {1, 1};
+  if (int rc = finish_into(d, part, dev_out, nblk, 2, ops2, norms_out)) return rc;
+  if (p) {
+    DiagLaunch L{d, p, W, nblk_diag, part};
+    if (int rc = dispatch(d, L)) return rc;
+    const int ops4[4] = {0, 0, 1, 2};
+    double dg[4];
+    if (int rc = finish_into(d, part, dev_out, nblk_diag, 4, ops4, dg)) return rc;
+    norms_out[2] = dg[0];
+    norms_out[3] = 100.0 * dg[1] / d->mesh->measure;
+  } else {
+    norms_out[2] = norms_out[3] = 0.0;
+  }
+  return BSW_OK;
+}
+
 int bsw_diagnostics(bsw_disc d, const bsw_params* p, const void* W, double* out4) {
   if (!d || !p || !W || !out4) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
   const int nblk = red_blocks(d->mesh->n_el);
   if (int rc = ensure_part(d, (size_t)nblk * 4)) return rc;
-  DiagLaunch L{d, p, W, nblk};
+  DiagLaunch L{d, p, W, nblk, d->part};
   if (int rc = dispatch(d, L)) return rc;
   const int ops[4] = {0, 0, 1, 2};
   if (int rc = finish(d, nblk, 4, ops, out4)) return rc;
