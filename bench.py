@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--serve-steps", type=int, default=3,
                     help="time steps per served request (each draw's horizon is cut to this many steps)")
     ap.add_argument("--tile-policy", type=int, default=-1, choices=[-1, 0, 1, 2],
-                    help="element-tile shape: -1 autotune (default), 0/1/2 force 128/256/512 lanes "
+                    help="element-pass variant: -1 autotune (default), 0/1/2 force one (triangles: occupancy "
+                         "target of 1/2/3 waves per SIMD) "
                          "(profiling runs repeat the shape the autotuner picked in the bench run)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solve: a 256 MiB device copy (counter calibration) and 20 launches of each hot "
@@ -500,10 +501,10 @@ def main():
     # the element-tile shape the autotuner kept for this pass (Jacobian, FP64, P2, this size class)
     tuned = [r for r in bsw.tile_table() if (r["dim"], r["P"], r["bytes"], r["mode"]) == (2, problem.P, 8, 1)
              and r["size_class"] == int(math.floor(math.log2(n_el)))]
-    lanes = tuned[0]["lanes"] if tuned else 256
+    variant = tuned[0]["variant"] if tuned and tuned[0]["variant"] >= 0 else 1
     roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES.get(dominant),
-            "kernel": f"kb_elem<2,{problem.P},double,1,{lanes}> (matrix-free Jacobian apply inside the solve: "
+            "kernel": f"kb_elem<2,{problem.P},double,1,{variant}> (matrix-free Jacobian apply inside the solve: "
                       "one element pass in the autotuned tile shape, the neighbours' side of x evaluated in it)",
             "bytes_per_launch": k["bytes"], "launch_seconds": k["seconds"],
             "launches_timed": st.get("jac_apply_launches", 0)}
@@ -553,7 +554,7 @@ def main():
         "hbm_resident": hbm,
         "tile_autotuner": [{"pass": "jacobian" if r["mode"] else "residual",
                             "precision": "f64" if r["bytes"] == 8 else "f32", "size_class": r["size_class"],
-                            "lanes": r["lanes"],
+                            "variant": r["variant"],
                             "best_us": {str(n): round(v, 2) for n, v in r["best_us"].items()}}
                            for r in bsw.tile_table() if r["dim"] == 2 and r["P"] == problem.P],
     }

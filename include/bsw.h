@@ -312,19 +312,23 @@ int bsw_solve(bsw_disc disc, const bsw_params* prm, const bsw_solve_opts* opts, 
 
 /* ---------------------------------------------------------------- element-tile autotuner */
 /* The element pass of batched and whole solves (bsw_solve and the server)
- * runs in one of three tile shapes: workgroups of 128, 256 or 512 lanes, each
- * taking as many elements as it has lanes per (volume + face) point set.
- * All shapes give the same bits.  Per (dimension, order, precision,
- * residual or Jacobian pass, size class floor(log2 of the launch's element
- * count)) the library times the first launches of every shape (HIP events,
- * read without blocking) and keeps the fastest for the process.
- * bsw_tile_policy: -1 autotune (default), 0/1/2 force 128/256/512 lanes;
+ * runs in one of three variants.  On triangles: a workgroup of 4 waves on a
+ * tile of 64 elements (one lane per element), compiled for at least 1, 2 or
+ * 3 resident waves per SIMD (register budgets of 512, 256 and 168 per lane).
+ * In 1-D: workgroups of 128, 256 or 512 lanes, each taking as many elements
+ * as it has lanes per (volume + face) point set.  All variants give the same
+ * bits.  Per (dimension, order, precision, residual or Jacobian pass, size
+ * class floor(log2 of the launch's element count)) the library times the
+ * first launches of every variant (HIP events, read without blocking) and
+ * keeps the fastest for the process.  The single-call entry points
+ * (bsw_operator_apply, bsw_jacobian_apply) use variant 1.
+ * bsw_tile_policy: -1 autotune (default), 0/1/2 force a variant;
  * *previous (may be NULL) receives the old policy.  Process-wide. */
 int bsw_tile_policy(int policy, int* previous);
 /* Up to max_rows rows of 10 doubles (host): {dim, P, bytes per real, pass
- * (0 residual, 1 Jacobian), size class, chosen lanes (-1 while measuring),
- * best microseconds of the 128/256/512-lane shapes (-1 if not yet timed),
- * timed launches}; *n_rows receives the number of table entries. */
+ * (0 residual, 1 Jacobian), size class, chosen variant (-1 while measuring),
+ * best microseconds of variants 0, 1, 2 (-1 if not yet timed), timed
+ * launches}; *n_rows receives the number of table entries. */
 int bsw_tile_table(double* rows, int max_rows, int* n_rows);
 
 /* ---------------------------------------------------------------- solve server (batched, continuous) */

@@ -457,7 +457,8 @@ class _ReqArrays:
 
 
 def tile_policy(policy: int) -> int:
-    """-1: autotune the element-tile shape; 0/1/2: force 128/256/512 lanes.
+    """-1: autotune the element-pass variant; 0/1/2: force one (triangles:
+    occupancy target 1/2/3 waves per SIMD; 1-D: 128/256/512 lanes).
     Returns the previous policy."""
     prev = C.c_int(0)
     if lib().bsw_tile_policy(int(policy), C.byref(prev)) != BSW_OK:
@@ -475,7 +476,7 @@ def tile_table() -> list:
     out = []
     for r in rows[: n.value]:
         out.append(dict(dim=int(r[0]), P=int(r[1]), bytes=int(r[2]), mode=int(r[3]), size_class=int(r[4]),
-                        lanes=int(r[5]), best_us={128: r[6], 256: r[7], 512: r[8]}, timed=int(r[9])))
+                        variant=int(r[5]), best_us={0: r[6], 1: r[7], 2: r[8]}, timed=int(r[9])))
     return out
 
 

@@ -41,8 +41,9 @@ int n_modes(int dim, int P) { return dim == 1 ? P + 1 : (P + 1) * (P + 2) / 2; }
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // ------------------------------------------------------------ tile autotuner
-// Picks the element-tile shape (workgroup size of the element pass, kTileNT)
-// per (dimension, order, precision, residual or Jacobian, size class).  The
+// Picks the element-tile variant of the element pass (elem_tile: on triangles
+// the occupancy target, in 1-D the workgroup size) per (dimension, order,
+// precision, residual or Jacobian, size class).  The
 // first launches of a key rotate through the shapes; the caller brackets each
 // with a HIP event pair and hands the pair over once both are recorded.
 // Completed pairs are read without blocking (hipEventQuery) on later picks,
@@ -227,9 +228,9 @@ struct BatchEngine {
   int init(bsw_ctx ctx, int dim_, int P_, int M_) {
     c = ctx; dim = dim_; P = P_; M = M_;
     auto fs = [&]<int D, int PP, class TT>() -> int {
-      EBv[0] = Blk<D, PP, kTileNT[0]>::EB;
-      EBv[1] = Blk<D, PP, kTileNT[1]>::EB;
-      EBv[2] = Blk<D, PP, kTileNT[2]>::EB;
+      EBv[0] = etile_eb<D, PP, 0>();
+      EBv[1] = etile_eb<D, PP, 1>();
+      EBv[2] = etile_eb<D, PP, 2>();
       BS = Shape<D, PP>::BS;
       NFNFC = Shape<D, PP>::NF * Shape<D, PP>::NFC;
       return BSW_OK;
@@ -346,17 +347,17 @@ struct BatchEngine {
       ta = tb = nullptr;
     }
     auto f = [&]<int D, int PP, class TT>() -> int {
-      auto go = [&]<int NT>() {
+      auto go = [&]<int V>() {
         if (mode == 0)
-          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 0, NT>), dim3(nt), dim3(NT), 0, c->stream, t_start, t_stop, 0,
-                                d_desc, S, sW, sX, (int)B_BOLD, sOut);
+          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 0, V>), dim3(nt), dim3(etile_nt<D, V>()), 0, c->stream,
+                                t_start, t_stop, 0, d_desc, S, sW, sX, (int)B_BOLD, sOut);
         else
-          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 1, NT>), dim3(nt), dim3(NT), 0, c->stream, t_start, t_stop, 0,
-                                d_desc, S, sW, sX, (int)B_BOLD, sOut);
+          hipExtLaunchKernelGGL((kb_elem<D, PP, TT, 1, V>), dim3(nt), dim3(etile_nt<D, V>()), 0, c->stream,
+                                t_start, t_stop, 0, d_desc, S, sW, sX, (int)B_BOLD, sOut);
       };
-      if (v == 0) go.template operator()<kTileNT[0]>();
-      else if (v == 1) go.template operator()<kTileNT[1]>();
-      else go.template operator()<kTileNT[2]>();
+      if (v == 0) go.template operator()<0>();
+      else if (v == 1) go.template operator()<1>();
+      else go.template operator()<2>();
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
@@ -1428,7 +1429,7 @@ int bsw_tile_table(double* rows, int max_rows, int* n_rows) {
       r[2] = (double)((k >> 8) & 255);
       r[3] = (double)((k >> 16) & 255);
       r[4] = (double)((k >> 24) & 255);
-      r[5] = E.choice >= 0 ? (double)kTileNT[E.choice] : -1.0;
+      r[5] = (double)E.choice;
       for (int v = 0; v < kTileShapes; ++v) r[6 + v] = E.n[v] ? 1e3 * E.best_ms[v] : -1.0;
       r[9] = (double)(E.n[0] + E.n[1] + E.n[2]);
     }

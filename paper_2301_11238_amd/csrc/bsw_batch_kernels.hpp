@@ -16,7 +16,7 @@
 
 #include <cstdint>
 
-#include "bsw_kernels.hpp"
+#include "bsw_elem2.hpp"
 
 namespace bsw {
 
@@ -114,18 +114,18 @@ __global__ void __launch_bounds__(256) kb_trace(const InstDesc<T>* __restrict__ 
 // MODE 0: R = residual(W; b_old); MODE 1: y = J(W) x with the traces of W in
 // trL (the neighbours' side of the pass's argument, W or x, is evaluated in
 // the pass from their coefficients)
-// NT: the element-tile shape (workgroup size), chosen by the autotuner
-template <int D, int P, class T, int MODE, int NT>
-__global__ void __launch_bounds__(NT, (elem_waves<D, P, T>())) kb_elem(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW, int sX,
-                                               int sB, int sOut) {
+// V: the element-tile shape (elem_tile's variant), chosen by the autotuner
+template <int D, int P, class T, int MODE, int V>
+__global__ void __launch_bounds__((etile_nt<D, V>()), (etile_minw<D, P, T, V>())) kb_elem(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW, int sX,
+                                                     int sB, int sOut) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int ai = bset_find(A, b);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int j = A.jv[ai];
-  const int e0 = (b - A.tile0[ai]) * Blk<D, P, NT>::EB;
-  elem_blocked_tile<D, P, T, MODE, NT>(bslot(I, sW, j), MODE == 1 ? bslot(I, sX, j) : nullptr,
-                                   MODE == 0 ? bslot(I, sB, j) : nullptr, bslot(I, sOut, j),
-                                   MODE == 0 ? nullptr : I.trL, I.m, I.p, e0);
+  const int e0 = (b - A.tile0[ai]) * etile_eb<D, P, V>();
+  elem_tile<D, P, T, MODE, V>(bslot(I, sW, j), MODE == 1 ? bslot(I, sX, j) : nullptr,
+                              MODE == 0 ? bslot(I, sB, j) : nullptr, bslot(I, sOut, j),
+                              MODE == 0 ? nullptr : I.trL, I.m, I.p, e0);
 }
 
 template <int D, int P, class T>

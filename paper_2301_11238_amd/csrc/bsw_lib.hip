@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "../../include/bsw.h"
-#include "bsw_kernels.hpp"
+#include "bsw_elem2.hpp"
 #include "ref_element.hpp"
 
 namespace bsw {
@@ -516,7 +516,7 @@ struct OpLaunch {
     hipStream_t st = d->mesh->ctx->stream;
     if (int rc = sync_dirtab<T>(d, *p)) return rc;
     // one element pass: it evaluates the neighbours' side of W itself
-    hipLaunchKernelGGL((k_elem_blocked<D, P, T, 0>), grid1(m.n_el, Blk<D, P>::EB), dim3(256), 0, st, (const T*)W,
+    hipLaunchKernelGGL((k_elem<D, P, T, 0, 1>), grid1(m.n_el, etile_eb<D, P, 1>()), dim3(etile_nt<D, 1>()), 0, st, (const T*)W,
                        (const T*)nullptr, (const T*)bold, (T*)R, (const T*)nullptr, m,
                        devparams<T>(*p, dt, (const T*)d->dirtab));
     HIPCHK(d->mesh->ctx, hipGetLastError());
@@ -545,11 +545,11 @@ struct JacApplyLaunch {
   int operator()() {
     auto m = view<T>(d);
     hipStream_t st = d->mesh->ctx->stream;
-    const dim3 ge = grid1(m.n_el, Blk<D, P>::EB);
+    const dim3 ge = grid1(m.n_el, etile_eb<D, P, 1>());
     const T* tL = (const T*)d->trL;
     if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
     const auto prm = devparams<T>(d->lin_prm, d->lin_dt, (const T*)d->dirtab);
-    hipExtLaunchKernelGGL((k_elem_blocked<D, P, T, 1>), ge, dim3(256), 0, st, ev_start, ev_stop, 0,
+    hipExtLaunchKernelGGL((k_elem<D, P, T, 1, 1>), ge, dim3(etile_nt<D, 1>()), 0, st, ev_start, ev_stop, 0,
                           (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, tL, m, prm);
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;

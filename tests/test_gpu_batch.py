@@ -198,28 +198,29 @@ def test_cancel_and_invalid_requests(ctx):
 
 
 def test_tile_shapes_give_the_same_bits_and_autotuner_picks_one(ctx):
-    """The element pass in its 128-, 256- and 512-lane tile shapes gives the
-    same state bit for bit (each element's arithmetic is the same); with the
-    autotuner on, every shape is timed on live launches and one is kept."""
+    """The element pass in its three variants (triangles: occupancy targets of
+    1, 2 and 3 waves per SIMD for the same tile code) gives the same state bit
+    for bit; with the autotuner on, every variant is timed on live launches
+    and one is kept."""
     from paper_2301_11238_amd import bsw
-    case = MIX[4]  # P3
-    out = []
-    try:
-        for pol in (0, 1, 2, -1):
-            bsw.tile_policy(pol)
-            out.append(run_alone(ctx, case, bsw.BSW_FP64))
-    finally:
-        bsw.tile_policy(-1)
-    for W, st in out[1:]:
-        assert np.array_equal(W, out[0][0])
-        assert st["newton_total"] == out[0][1]["newton_total"]
+    for case in (MIX[4], MIX[0], MIX[5]):  # P3, P2, P1
+        out = []
+        try:
+            for pol in (0, 1, 2, -1):
+                bsw.tile_policy(pol)
+                out.append(run_alone(ctx, case, bsw.BSW_FP64))
+        finally:
+            bsw.tile_policy(-1)
+        for W, st in out[1:]:
+            assert np.array_equal(W, out[0][0]), case[0]
+            assert st["newton_total"] == out[0][1]["newton_total"]
     rows = [r for r in bsw.tile_table() if r["dim"] == 2 and r["P"] == 3 and r["bytes"] == 8]
     assert rows and any(r["mode"] == 1 for r in rows)
     for r in rows:
-        if r["lanes"] > 0:
-            assert r["lanes"] in (128, 256, 512)
+        if r["variant"] >= 0:
+            assert r["variant"] in (0, 1, 2)
             best = min(v for v in r["best_us"].values() if v > 0)
-            assert r["best_us"][r["lanes"]] == best
-    assert any(r["lanes"] > 0 for r in rows if r["mode"] == 1)
+            assert r["best_us"][r["variant"]] == best
+    assert any(r["variant"] >= 0 for r in rows if r["mode"] == 1)
     with pytest.raises(bsw.BswError):
         bsw.tile_policy(3)
