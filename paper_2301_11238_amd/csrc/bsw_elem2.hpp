@@ -30,6 +30,21 @@
 
 namespace bsw {
 
+// Entry e of row `row` of an element-fastest array with n columns.  The row
+// base is wave-uniform (scalar registers) and the byte offset of e is formed
+// in 32 bits (a row block of one call stays below 4 GiB), so a load needs
+// little address arithmetic per lane.
+template <class T>
+__device__ __forceinline__ T rowld(const T* __restrict__ a, int row, int n, unsigned e) {
+  const char* r = reinterpret_cast<const char*>(a + (size_t)row * (size_t)n);
+  return *reinterpret_cast<const T*>(r + e * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ T& rowref(T* a, int row, int n, unsigned e) {
+  char* r = reinterpret_cast<char*>(a + (size_t)row * (size_t)n);
+  return *reinterpret_cast<T*>(r + e * (unsigned)sizeof(T));
+}
+
 template <int P, class T, int MODE, int NW>
 struct E2 {
   using S = Shape<2, P>;
@@ -39,7 +54,7 @@ struct E2 {
   static constexpr int NVI = 10;                              // volume integrands per point
   static constexpr int NFI = 5;                               // face integrands per point
   static constexpr int QW = (S::NQ + NW - 1) / NW;            // volume points per wave
-  static constexpr int PC = MODE == 0 ? (P < 3 ? S::NFQ : 2) : 1;  // face points per chunk (register budget)
+  static constexpr int PC = P < 3 ? S::NFQ : 2;               // face points per chunk (register budget)
   static constexpr int NCH = (S::NFQ + PC - 1) / PC;          // chunks per face
   static constexpr int GS = (Shape<2, P>::NF + NW - 1) / NW;  // output fields per wave
   static constexpr int LDS = (S::NQ * NVI > NFP * NFI ? S::NQ * NVI : NFP * NFI) * EB;
@@ -228,20 +243,20 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int e = e0 + lane;
   const bool live = e < n;
-  const int ec = live ? e : n - 1;  // dead lanes of a ragged tail read a valid element
+  const unsigned ec = live ? e : n - 1;  // dead lanes of a ragged tail read a valid element
   __shared__ T sI[C::LDS];
 
   // -------------------------------------------------- stage 1: face integrands
   for (int u = w; u < S::NFC * C::NCH; u += NW) {
     const int fc = u / C::NCH, r0 = (u % C::NCH) * C::PC;
-    const int code = m.nbr[(size_t)fc * n + ec];
+    const int code = rowld(m.nbr, fc, n, ec);
     const bool inner = code >= 0;
-    const int nb = inner ? (code >> 2) : ec;
+    const unsigned nb = inner ? (unsigned)(code >> 2) : ec;
     const int gf = inner ? (code & 3) : 0;
     T nvec[2];
-    nvec[0] = m.nrm[(size_t)(fc * 2 + 0) * n + ec];
-    nvec[1] = m.nrm[(size_t)(fc * 2 + 1) * n + ec];
-    const T hl = m.hlen[(size_t)fc * n + ec];
+    nvec[0] = rowld(m.nrm, fc * 2 + 0, n, ec);
+    nvec[1] = rowld(m.nrm, fc * 2 + 1, n, ec);
+    const T hl = rowld(m.hlen, fc, n, ec);
     // the neighbour's basis at its own face points, per lane (point order
     // reversed along the shared edge)
     T tnb[C::PC][S::NP];
@@ -257,32 +272,30 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
     // index is wave-uniform, so placing the values is a scalar branch
 #pragma unroll 1
     for (int f = 0; f < S::NF; ++f) {
-      T c[S::NP], cn[S::NP], cx[TAN ? S::NP : 1];
+      // residual: the element's and the neighbour's side of W from their
+      // coefficients; Jacobian: those of x from their coefficients, those of
+      // the linearisation state W from its stored traces (below)
+      const T* __restrict__ A = TAN ? x : W;
+      T c[S::NP], cn[S::NP];
 #pragma unroll
       for (int i = 0; i < S::NP; ++i) {
-        c[i] = W[(size_t)(f * S::NP + i) * n + ec];
-        if constexpr (!TAN) cn[i] = W[(size_t)(f * S::NP + i) * n + nb];
-        else {
-          cn[i] = x[(size_t)(f * S::NP + i) * n + nb];
-          cx[i] = x[(size_t)(f * S::NP + i) * n + ec];
-        }
+        c[i] = rowld(A, f * S::NP + i, n, ec);
+        cn[i] = rowld(A, f * S::NP + i, n, nb);
       }
 #pragma unroll
       for (int j = 0; j < C::PC; ++j) {
         const int rr = r0 + j < S::NFQ ? r0 + j : S::NFQ - 1;
-        T s1 = T(0), s2 = T(0), s3 = T(0);
+        T s1 = T(0), s2 = T(0);
 #pragma unroll
         for (int i = 0; i < S::NP; ++i) {
           s1 += tb.fphi[fc][rr][i] * c[i];
           s2 += tnb[j][i] * cn[i];
-          if constexpr (TAN) s3 += tb.fphi[fc][rr][i] * cx[i];
         }
 #pragma unroll
         for (int ff = 0; ff < S::NF; ++ff)
           if (ff == f) {
-            Xm[j][ff] = s1;
-            if constexpr (!TAN) Xp[j][ff] = s2;
-            else { dXp[j][ff] = s2; dXm[j][ff] = s3; }
+            if constexpr (!TAN) { Xm[j][ff] = s1; Xp[j][ff] = s2; }
+            else { dXm[j][ff] = s1; dXp[j][ff] = s2; }
           }
       }
     }
@@ -291,10 +304,12 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
       const int rr = r0 + j;
       if (rr >= S::NFQ) break;
       if constexpr (TAN) {
-        // the neighbour's side of the linearisation state from its traces
+        // both sides of the linearisation state from its traces
 #pragma unroll
-        for (int f = 0; f < S::NF; ++f)
-          Xp[j][f] = trW[(size_t)(f * C::NFP + gf * S::NFQ + (S::NFQ - 1 - rr)) * n + nb];
+        for (int f = 0; f < S::NF; ++f) {
+          Xm[j][f] = rowld(trW, f * C::NFP + fc * S::NFQ + rr, n, ec);
+          Xp[j][f] = rowld(trW, f * C::NFP + (S::NFQ - 1 - rr), n, (unsigned)(gf * S::NFQ) * (unsigned)n + nb);
+        }
       }
       Pt<2, T> sm, sp, dsm, dsp;
       unpack<2, T>(Xm[j], sm);
@@ -332,7 +347,7 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
 #pragma unroll
     for (int fc = 0; fc < 3; ++fc)
 #pragma unroll
-      for (int a = 0; a < 2; ++a) nv[fc][a] = m.nrm[(size_t)(fc * 2 + a) * n + ec];
+      for (int a = 0; a < 2; ++a) nv[fc][a] = rowld(m.nrm, fc * 2 + a, n, ec);
 #pragma unroll
     for (int s = 0; s < C::GS; ++s) {
       const int f = w + s * NW;
@@ -351,8 +366,17 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
       T c[S::NP], cx[TAN ? S::NP : 1];
 #pragma unroll
       for (int i = 0; i < S::NP; ++i) {
-        c[i] = W[(size_t)(f * S::NP + i) * n + ec];
-        if constexpr (TAN) cx[i] = x[(size_t)(f * S::NP + i) * n + ec];
+        c[i] = rowld(W, f * S::NP + i, n, ec);
+        if constexpr (TAN) cx[i] = rowld(x, f * S::NP + i, n, ec);
+      }
+      // the mass terms of the wave's own rows of field f: |J| h_i / dt on the
+      // depth rows, |J| E_i on the gradient rows (of the pass's argument)
+#pragma unroll
+      for (int s = 0; s < C::GS; ++s) {
+        if (w + s * NW != f || (f != 0 && f < 3)) continue;
+        const T sc = f == 0 ? geo.detJ * p.inv_dt : geo.detJ;
+#pragma unroll
+        for (int i = 0; i < S::NP; ++i) acc[s][i] += sc * (TAN ? cx[i] : c[i]);
       }
 #pragma unroll
       for (int j = 0; j < C::QW; ++j) {
@@ -405,17 +429,18 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
     if (f >= S::NF) break;
     e2_contract_volume<P, T>(tb, sI, lane, f, geo, acc[s]);
     if (!live) continue;
+    const unsigned eu = (unsigned)e;
 #pragma unroll
     for (int i = 0; i < S::NP; ++i) {
-      const size_t at = (size_t)(f * S::NP + i) * n + e;
-      const T cf = arg[at];
+      const int row = f * S::NP + i;
       T v = acc[s][i];
-      if (f == 0) v += geo.detJ * p.inv_dt * cf;
-      else if (f >= 3) v += geo.detJ * cf;
       if constexpr (!TAN) {
-        if (f < 3) v -= bold[at];
+        if (f < 3) v -= rowld(bold, row, n, eu);
       }
-      out[at] = row_unused<2, T>(m, f, i) ? cf : v;
+      // unused modes of a lower-order field (wave-uniform test): the row is
+      // the coefficient itself
+      if (row_unused<2, T>(m, f, i)) v = rowld(arg, row, n, eu);
+      rowref(out, row, n, eu) = v;
     }
   }
 }
