@@ -15,7 +15,7 @@ stream).  The Jacobian-apply rate is reported beside it.
 
 One step (--steps, --warmup) = one pass over the whole hot path on the same
 mesh and state: b_old (a1), the residual (a2-a4), the linearisation (a5:
-traces, diagonal blocks, their inverses), one restarted-GMRES cycle of 30
+traces, diagonal blocks, their Schur-complement factors), one restarted-GMRES cycle of 30
 block-Jacobi-preconditioned matrix-free Jacobian applies (a5, a7), the Newton
 update with its line search and the FP64 reductions (a6): one Newton
 iteration of one backward-Euler time step.  ms_per_step is its time.
@@ -208,8 +208,8 @@ def hbm_resident(problem, mesh, disc, cp, dt, stream, op_bytes, jac_bytes, min_t
 def hot_path_passes(disc, cp, W, dt, args):
     """`warmup` untimed and `steps` timed passes over the whole hot path: each
     one backward-Euler time step cut to one Newton iteration whose GMRES runs
-    one cycle of 30 Arnoldi steps (b_old, residual, linearisation with block
-    inverses, 30 preconditioned Jacobian applies with Gram-Schmidt, the
+    one cycle of 30 Arnoldi steps (b_old, residual, linearisation with the
+    block-Jacobi factors, 30 preconditioned Jacobian applies with Gram-Schmidt, the
     update with its line search, FP64 norms and diagnostics)."""
     import torch
     from paper_2301_11238_amd import bsw
@@ -558,6 +558,8 @@ def main():
     op_bytes = bytes_per_element(2, problem.P, 8) * n_el
     jac_bytes = jac_bytes_per_element(2, problem.P, 8) * n_el
     bs = disc.nf * disc.np
+    nv, nu, ne = 3 * disc.np, 2 * disc.np, 4 * disc.np
+    nb_schur = nv * nv + 2 * nu * ne + ne  # block-Jacobi factor numbers per element
 
     def single_set_kernels(Wk):
         b = disc.step_begin(cp, dt, Wk)
@@ -571,10 +573,11 @@ def main():
         return {
             "operator": dict(seconds=t_op, bytes=op_bytes),
             "jacobian_apply": dict(seconds=t_jac, bytes=jac_bytes),
-            "block_jacobi_apply": dict(seconds=t_pc, bytes=(4 * bs * bs + 2 * 8 * bs) * n_el),
-            # traces of W, the FP64 diagonal blocks (written, then read by the
-            # inversion) and their FP32 inverses
-            "linearisation": dict(seconds=t_lin, bytes=(8 + 8 + 4) * bs * bs * n_el),
+            # the FP32 factors (S^-1, A_UE, D^-1 A_EU, D^-1), x and y
+            "block_jacobi_apply": dict(seconds=t_pc, bytes=(4 * nb_schur + 2 * 8 * bs) * n_el),
+            # the FP64 diagonal blocks (written), the parts of them the factor
+            # build reads, and the FP32 factors
+            "linearisation": dict(seconds=t_lin, bytes=(8 * bs * bs + 8 * nb_schur + 4 * nb_schur) * n_el),
         }
 
     if args.kernels_only:
@@ -626,7 +629,7 @@ def main():
                    "n_el": n_el, "n_dof": n_dof, "dt": dt,
                    "value_definition": "n_dof / median HBM-resident operator-apply time",
                    "step": "one pass over the whole hot path: b_old, residual, linearisation (traces, diagonal "
-                           "blocks, FP32 inverses), one GMRES(30) cycle of preconditioned matrix-free "
+                           "blocks, FP32 Schur-complement factors), one GMRES(30) cycle of preconditioned matrix-free "
                            "Jacobian applies, the Newton update with its line search, FP64 reductions",
                    "per_step": {k: v / args.steps for k, v in tot.items()},
                    "operator_dof_updates_per_s": value,

@@ -254,15 +254,19 @@ int bsw_operator_apply(bsw_disc disc, const bsw_params* prm, double dt, const vo
 /* ---------------------------------------------------------------- element-block Jacobian (Appendix A) */
 /* Records W (device pointer, kept by reference: the caller must not change or
  * free it until the next linearize), the parameters and dt; assembles the
- * diagonal blocks dR_e/dW_e of Eq. Newton and inverts them (Gauss-Jordan with
- * partial pivoting, inverses kept in FP32) for the block-Jacobi preconditioner. */
+ * diagonal blocks dR_e/dW_e of Eq. Newton and factors them for the
+ * block-Jacobi preconditioner through the Schur complement of the stress block
+ * (whose own block is the diagonal element mass matrix): the inverse of the
+ * depth-velocity Schur complement (Gauss-Jordan with partial pivoting), the
+ * velocity-stress couplings and the diagonal, kept in FP32. */
 int bsw_jacobian_linearize(bsw_disc disc, const bsw_params* prm, double dt, const void* W);
 /* y = (dR/dW)(W) x, the directional derivative including the face coupling to
  * neighbours (matrix-free): exact, HLL wave speeds included, or with them held
  * fixed when prm->jac_frozen was set at linearize.  BSW_E_STATE before the
  * first linearize. */
 int bsw_jacobian_apply(bsw_disc disc, const void* x, void* y);
-/* y = blockdiag(dR_e/dW_e)^{-1} x using the inverses of the last linearize. */
+/* y = blockdiag(dR_e/dW_e)^{-1} x from the factors of the last linearize
+ * (FP32 factors, FP64 arithmetic). */
 int bsw_precond_apply(bsw_disc disc, const void* x, void* y);
 /* Writes the unfactored diagonal blocks of the last linearize to blocks
  * (device, [n_el][bs][bs] row-major, bs = n_f n_p, row/column index f*n_p+i). */
@@ -339,7 +343,7 @@ int bsw_tile_table(double* rows, int max_rows, int* n_rows);
  * solves are resident, and retires finished solves (state copied to host
  * memory, device memory released).  Resident solves of the same order,
  * precision and restart length form one batch: every stage of their time
- * steps (b_old, residual, Jacobian blocks and inverses, block-Jacobi and
+ * steps (b_old, residual, Jacobian blocks and their factors, block-Jacobi and
  * matrix-free Jacobian applies, Krylov vector updates, reductions) is one
  * kernel launch over all of them, while Newton, backtracking and GMRES
  * decisions stay per solve.  Reductions are per solve with a fixed shape, so
@@ -376,7 +380,7 @@ typedef struct {
 } bsw_solve_request;
 
 /* Device bytes a request occupies while resident: state and 11 + gmres_m
- * work vectors, the diagonal Jacobian blocks and their inverses, reduction
+ * work vectors, the diagonal Jacobian blocks and their FP32 factors, reduction
  * partials, mesh arrays and the bed coefficients (counted for every request).
  * -1 for an invalid request. */
 int64_t bsw_request_footprint(const bsw_solve_request* req);

@@ -126,7 +126,8 @@ TileTuner& tile_tuner() {
 }
 
 // Device bytes one resident instance takes: state and Krylov vectors,
-// diagonal blocks and their inverses, face traces, reduction partials, mesh.
+// diagonal blocks and their FP32 block-Jacobi factors, face traces, reduction
+// partials, mesh.
 int64_t instance_bytes(int64_t n_el, int dim, int P, int precision, int M) {
   const int64_t w = precision == BSW_FP64 ? 8 : 4;
   const int64_t nf = 1 + dim + dim * dim;
@@ -136,7 +137,7 @@ int64_t instance_bytes(int64_t n_el, int dim, int P, int precision, int M) {
   const int64_t ld = round_up(len, 64);
   const int64_t ntile = (len + kVT - 1) / kVT, ntile_e = (n_el + 255) / 256;
   int64_t b = (kBaseSlots + M + 1) * ld * w;
-  b += bs * bs * n_el * (w + 4);  // diagonal blocks and their FP32 inverses
+  b += bs * bs * n_el * w + (int64_t)schur_numbers(dim, n_modes(dim, P)) * n_el * 4;  // blocks, FP32 factors
   b += nf * nfp * n_el * w;  // face traces of the linearisation state
   b += std::max<int64_t>(std::max<int64_t>(66 * ntile, 4 * ntile_e), 4096) * 8;
   const int64_t geo = dim * dim + 1 + (dim + 1) * (dim + 1);
@@ -261,13 +262,13 @@ struct BatchEngine {
   }
 
   // ------------------------------------------------------------ launch sets
-  enum Kind { K_ETILE, K_E256, K_E1, K_ITEM, K_VEC, K_ONE, K_TRACE, K_COLS };
+  enum Kind { K_ETILE, K_E256, K_SCHUR, K_PREC, K_VEC, K_ONE, K_TRACE, K_COLS };
   int tiles_of(const BInst<T>* I, int kind) const {
     switch (kind) {
       case K_ETILE: return (int)((I->n_el + eb_cur - 1) / eb_cur);
       case K_E256: return I->ntile_e;
-      case K_E1: return (int)I->n_el;
-      case K_ITEM: return (int)(BS * ((I->n_el + 255) / 256));  // row tiles (row_tile)
+      case K_SCHUR: return (int)((I->n_el + kSchurEPB - 1) / kSchurEPB);  // block-Jacobi factor builds
+      case K_PREC: return (int)((I->n_el + kPrecEB - 1) / kPrecEB);       // block-Jacobi applies
       case K_VEC: return I->ntile;
       case K_TRACE: return (int)((NFNFC * I->n_el + 255) / 256);
       case K_COLS: return cols_tiles_for(BS, (int)I->n_el);  // jac_columns_elem workgroups
@@ -380,20 +381,18 @@ struct BatchEngine {
     return elem_pass(mode, L, nullptr, sW, sX, sOut);
   }
   // traces of the linearisation state for all of L; diagonal blocks and their
-  // inverses for the instances in B (a subset of L)
+  // block-Jacobi factors for the instances in B (a subset of L)
   int linearize(const std::vector<int>& L, const std::vector<int>& B) {
     if (int rc = trace(L, B_W)) return rc;
     BatchSet S;
-    const int nt = build(S, B, K_E1);
+    const int nt = build(S, B, K_SCHUR);
     if (!nt) return BSW_OK;
     auto f = [&]<int D, int PP, class TT>() -> int {
-      using Sh = Shape<D, PP>;
       BatchSet Sc;
       const int ncol = build(Sc, B, K_COLS);
       hipLaunchKernelGGL((kb_jac_columns<D, PP, TT>), dim3(ncol), dim3(256), 0, c->stream, d_desc, Sc, (int)B_W);
       HIPCHK(c, hipGetLastError());
-      hipLaunchKernelGGL((kb_block_inverse<Sh::BS, TT>), dim3(nt), dim3(inv_threads<Sh::BS>()), 0, c->stream, d_desc,
-                         S);
+      hipLaunchKernelGGL((kb_schur_build<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S);
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
@@ -402,11 +401,10 @@ struct BatchEngine {
   }
   int prec(const std::vector<int>& L, int sX, int sY) {
     BatchSet S;
-    const int nt = build(S, L, K_ITEM);
+    const int nt = build(S, L, K_PREC);
     if (!nt) return BSW_OK;
     auto f = [&]<int D, int PP, class TT>() -> int {
-      using Sh = Shape<D, PP>;
-      hipLaunchKernelGGL((kb_block_apply<Sh::BS, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sX, sY);
+      hipLaunchKernelGGL((kb_prec_apply<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sX, sY);
       HIPCHK(c, hipGetLastError());
       return BSW_OK;
     };
@@ -540,9 +538,10 @@ struct BatchEngine {
     I->ntile = (int)((I->len + kVT - 1) / kVT);
     I->ntile_e = (int)((I->n_el + 255) / 256);
     const size_t nb = (size_t)BS * BS * I->n_el;
+    const size_t nf = (size_t)schur_numbers(dim, n_modes(dim, P)) * I->n_el;
     if (!I->ws && hipMalloc((void**)&I->ws, sizeof(T) * (size_t)ws_len(I->len, M)) != hipSuccess)
       return fail(c, BSW_E_OOM, "instance workspace");
-    if ((!d->blocks && hipMalloc(&d->blocks, nb * sizeof(float)) != hipSuccess) ||
+    if ((!d->blocks && hipMalloc(&d->blocks, nf * sizeof(float)) != hipSuccess) ||
         (!d->blocks_raw && hipMalloc(&d->blocks_raw, nb * sizeof(T)) != hipSuccess))
       return fail(c, BSW_E_OOM, "block-Jacobi storage");
     if (!I->part)
@@ -670,13 +669,12 @@ struct BatchEngine {
     timed_tick[pa] = tm;
     BatchSet S;
     // z = sigma_j M^{-1} V_j, sigma_j folded here for instances continuing prev
-    int nt = build(S, L, K_ITEM, jv);
+    int nt = build(S, L, K_PREC, jv);
     for (size_t a = 0; a < L.size(); ++a)
       S.rows[a] = prev && std::find(prev->mem.begin(), prev->mem.end(), L[a]) != prev->mem.end() ? 1 : 0;
     const int offN = kScN + (prev ? prev->parity : 0);
     auto fp = [&]<int D, int PP, class TT>() -> int {
-      using Sh = Shape<D, PP>;
-      hipLaunchKernelGGL((kb_prec_krylov<Sh::BS, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sc, sch_dev,
+      hipLaunchKernelGGL((kb_prec_krylov<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sc, sch_dev,
                          offN, (int)B_V0, (int)B_Z);
       HIPCHK(c, hipGetLastError());
       return BSW_OK;

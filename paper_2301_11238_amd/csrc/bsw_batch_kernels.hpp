@@ -56,7 +56,7 @@ struct InstDesc {
   int64_t ld;
   int64_t len;      // n_f N_p n_el
   int64_t len_v;    // (1 + D) N_p n_el: the entries of the first 1 + D fields
-  float* blk;       // block-Jacobi inverses (FP32), [row][col][n_el]
+  float* blk;       // block-Jacobi factors (FP32), [number][n_el]
   T* blk_raw;       // diagonal blocks, [n_el][row][col]
   T* trL;           // face traces of the linearisation state
   double* part;     // reduction partials, [row][tile]
@@ -135,24 +135,25 @@ __global__ void __launch_bounds__(256) kb_jac_columns(const InstDesc<T>* __restr
   jac_columns_elem<D, P, T>(bslot(I, sW, 0), I.trL, I.blk_raw, I.m, I.p, blockIdx.x - A.tile0[ai]);
 }
 
-template <int BS, class T>
-__global__ void __launch_bounds__(inv_threads<BS>(), (inv_waves<BS, T>())) kb_block_inverse(const InstDesc<T>* __restrict__ ds, BatchSet A) {
+// block-Jacobi factors, four elements per workgroup (k_schur_build)
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) kb_schur_build(const InstDesc<T>* __restrict__ ds, BatchSet A) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int ai = bset_find(A, b);
   const InstDesc<T> I = ds[A.inst[ai]];
-  block_inverse_elem<BS, T>(I.blk_raw, I.blk, I.m.n_el, b - A.tile0[ai]);
+  const int e = (b - A.tile0[ai]) * kSchurEPB + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (e < I.m.n_el) schur_build_elem<D, P, T>(I.blk_raw, I.blk, I.m.n_el, e);
 }
 
-template <int BS, class T>
-__global__ void __launch_bounds__(256) kb_block_apply(const InstDesc<T>* __restrict__ ds, BatchSet A, int sX,
-                                                       int sY) {
-  const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int ai = bset_find(A, b);
+// y = M^{-1} x on Krylov slot j, 64 elements per workgroup (k_schur_apply)
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) kb_prec_apply(const InstDesc<T>* __restrict__ ds, BatchSet A, int sX,
+                                                      int sY) {
+  const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int j = A.jv[ai];
-  int row, e;
-  row_tile<BS>(b - A.tile0[ai], row, e);
-  if (e < I.m.n_el) block_apply_item<BS, T>(I.blk, bslot(I, sX, j), bslot(I, sY, j), I.m.n_el, row, e);
+  schur_apply_tile<D, P, T>(I.blk, bslot(I, sX, j), bslot(I, sY, j), I.m.n_el,
+                            ((int)blockIdx.x - A.tile0[ai]) * kPrecEB, [] { return 1.0; });
 }
 
 // mass, active area, max wave speed, min depth per 256-element tile
@@ -506,39 +507,27 @@ __global__ void __launch_bounds__(256) kb_normalize(const InstDesc<T>* __restric
 // Where A.rows[ai] is set, V_j was written by the previous step's
 // kb_normalize and its squared-norm partials are still in I.part: every
 // workgroup folds them (the fold of kb_rows_final, same order) into
-// sigma_j = 1 / ||V_j||, and the instance's first workgroup stores sigma_j and
-// the norm (row offN) in sc and its host mirror sch.  Elsewhere sigma_j is
-// read from sc.
-template <int BS, class T>
+// sigma_j = 1 / ||V_j||, after the loads of its first phase have gone out,
+// and the instance's first workgroup stores sigma_j and the norm (row offN)
+// in sc and its host mirror sch.  Elsewhere sigma_j is read from sc.
+template <int D, int P, class T>
 __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restrict__ ds, BatchSet A,
                                                        double* __restrict__ sc, double* __restrict__ sch, int offN,
                                                        int sV0, int sZ) {
-  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int ai = bset_find(A, b);
   const int slot = A.inst[ai];
   const InstDesc<T> I = ds[slot];
   const int j = A.jv[ai];
-  const int n = I.m.n_el;
-  int row, e;
-  row_tile<BS>(b - A.tile0[ai], row, e);
-  // the loads of the norm partials and of the block row times V_j go out
-  // before sigma is reduced (the product does not depend on it)
   const bool fold = A.rows[ai] != 0;
-  double acc = 0.0;
-  if (fold)
+  const bool first = b == A.tile0[ai];
+  auto sigma = [&]() -> double {
+    if (!fold) return sc[(int64_t)slot * kScStride + kScS + j];
+    double acc = 0.0;
     for (int t = threadIdx.x; t < I.ntile; t += 256) acc += I.part[t];
-  double s = 0.0;
-  if (e < n) {
-    const T* x = bslot(I, sV0, 0) + (int64_t)j * I.ld;
-    const float* Ai = I.blk + (size_t)row * BS * n + e;
-#pragma unroll
-    for (int c = 0; c < BS; ++c) s += (double)Ai[(size_t)c * n] * (double)x[(size_t)c * n + e];
-  }
-  double sgm;
-  if (fold) {
     const double nrm = sqrt(bred(acc, 0));
-    sgm = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    if (b == A.tile0[ai] && threadIdx.x == 0) {
+    const double sgm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    if (first && threadIdx.x == 0) {
       double* sd = sc + (int64_t)slot * kScStride;
       double* sh = sch + (int64_t)slot * kScStride;
       sd[kScS + j] = sgm;
@@ -546,10 +535,10 @@ __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restr
       sd[offN] = nrm;
       sh[offN] = nrm;
     }
-  } else {
-    sgm = sc[(int64_t)slot * kScStride + kScS + j];
-  }
-  if (e < n) bslot(I, sZ, 0)[(size_t)row * n + e] = (T)(sgm * s);
+    return sgm;
+  };
+  schur_apply_tile<D, P, T>(I.blk, bslot(I, sV0, 0) + (int64_t)j * I.ld, bslot(I, sZ, 0), I.m.n_el,
+                            (b - A.tile0[ai]) * kPrecEB, sigma);
 }
 
 // ------------------------------------------------------------------ per-instance reductions

@@ -30,21 +30,6 @@
 
 namespace bsw {
 
-// Entry e of row `row` of an element-fastest array with n columns.  The row
-// base is wave-uniform (scalar registers) and the byte offset of e is formed
-// in 32 bits (a row block of one call stays below 4 GiB), so a load needs
-// little address arithmetic per lane.
-template <class T>
-__device__ __forceinline__ T rowld(const T* __restrict__ a, int row, int n, unsigned e) {
-  const char* r = reinterpret_cast<const char*>(a + (size_t)row * (size_t)n);
-  return *reinterpret_cast<const T*>(r + e * (unsigned)sizeof(T));
-}
-template <class T>
-__device__ __forceinline__ T& rowref(T* a, int row, int n, unsigned e) {
-  char* r = reinterpret_cast<char*>(a + (size_t)row * (size_t)n);
-  return *reinterpret_cast<T*>(r + e * (unsigned)sizeof(T));
-}
-
 template <int P, class T, int MODE, int NW>
 struct E2 {
   using S = Shape<2, P>;

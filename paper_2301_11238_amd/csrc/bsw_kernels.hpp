@@ -10,6 +10,21 @@ namespace bsw {
 
 extern __constant__ __align__(16) unsigned char c_tables[kTabBytesTotal];
 
+// Entry e of row `row` of an element-fastest array with n columns.  The row
+// base is wave-uniform (scalar registers) and the byte offset of e is formed
+// in 32 bits (a row block of one call stays below 4 GiB), so a load needs
+// little address arithmetic per lane.
+template <class T>
+__device__ __forceinline__ T rowld(const T* __restrict__ a, int row, int n, unsigned e) {
+  const char* r = reinterpret_cast<const char*>(a + (size_t)row * (size_t)n);
+  return *reinterpret_cast<const T*>(r + e * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ T& rowref(T* a, int row, int n, unsigned e) {
+  char* r = reinterpret_cast<char*>(a + (size_t)row * (size_t)n);
+  return *reinterpret_cast<T*>(r + e * (unsigned)sizeof(T));
+}
+
 template <int D, int P, class T>
 __device__ __forceinline__ const Tab<D, P, T>& tab() {
   return *reinterpret_cast<const Tab<D, P, T>*>(c_tables + tab_offset_rt(D, P, sizeof(T) == 4));
@@ -586,14 +601,6 @@ __device__ __forceinline__ void elem_blocked_tile(const T* __restrict__ W, const
   }
 }
 
-template <int D, int P, class T, int MODE>
-__global__ void __launch_bounds__(256, (elem_waves<D, P, T>())) k_elem_blocked(const T* __restrict__ W, const T* __restrict__ x,
-                                                       const T* __restrict__ bold, T* __restrict__ out,
-                                                       const T* __restrict__ trW, MeshView<T> m, DevParams<T> p) {
-  elem_blocked_tile<D, P, T, MODE>(W, x, bold, out, trW, m, p,
-                                   xcd_tile(blockIdx.x, gridDim.x) * Blk<D, P>::EB);
-}
-
 // Tangent of the element residual along the unit vector of one own degree of
 // freedom, col = f * N_p + i (a column of the diagonal block): the neighbour's
 // side is held fixed.  wl: the element's coefficients (row f * N_p + i), in
@@ -712,31 +719,47 @@ __global__ void __launch_bounds__(256) k_jac_columns(const T* __restrict__ W, co
   jac_columns_elem<D, P, T>(W, trW, blocks, m, p, blockIdx.x);
 }
 
-// Inverse of one diagonal block per workgroup: Gauss-Jordan elimination with
-// partial pivoting on [A | I], in place.  Each lane keeps one row in
-// registers.  Rows are never swapped: the lane whose row supplies the pivot of
-// step k (largest |entry| in the current column among the rows not yet used,
-// lowest row on ties) supplies it to the other lanes, which subtract its
-// multiple: by lane reads into scalar registers when the block fits one wave,
-// through LDS (one barrier per step) when it spans two.  The register row is rotated by one position per step, so the
-// current column is always register 0 and the step body is the same for every
-// step (a loop, not BS unrolled copies): position j takes the updated entry of
-// position j + 1, and the last position takes the new column of the right-hand
-// part.  Pivot rows are not normalised when chosen; each lane divides its row
-// by its own pivot at the end, which commutes with the later eliminations.
-// After BS steps the lane that supplied pivot k holds row k of the inverse,
-// its position k' the column piv[k'].
-// The inverse is written element-fastest, Ainv[(row * BS + col) * n + e], so
-// the preconditioner apply is a coalesced batched mat-vec.  It is stored in
-// FP32 for both state precisions: the preconditioner only steers GMRES (the
-// Krylov residual uses the exact Jacobian), and its apply reads half the bytes.
-// Consecutive elements run on one XCD, so the elements that share a line of
-// the output fill it in the same L2.
-template <int BS>
-constexpr int inv_threads() { return 64 * ((BS + 63) / 64); }
-// waves per SIMD the inversion is compiled for (FP64 rows of 70 fit 3)
-template <int BS, class T>
-constexpr int inv_waves() { return BS > 64 && sizeof(T) == 8 ? 3 : 4; }
+// ---------------------------------------------------------------- block-Jacobi
+// The preconditioner is the inverse of the block diagonal of the Jacobian,
+// applied through the Schur complement of each block's stress part.  The
+// rows of a block split into the depth and velocity rows V (fields h, u;
+// NV = (1 + D) N_p, the velocity rows U = N_p .. NV - 1) and the stress rows E
+// (D^2 N_p).  The discrete equations fix three zero or diagonal parts:
+//  * the stress equations (Sec. 3, the mixed form of the velocity gradient)
+//    are algebraic and linear in E with the element mass matrix, which is
+//    |J| I for the orthonormal basis: A_EE = D is diagonal;
+//  * the depth equation does not involve E, and the stress equations do not
+//    involve h: A_hE = 0 and A_Eh = 0.
+// So the Schur complement S = A_VV - A_VE D^{-1} A_EV differs from A_VV only
+// in its U x U part, and the block solve z = A^{-1} x is
+//   z_V = S^{-1} (x_V - A_VE D^{-1} x_E),   z_E = D^{-1} x_E - D^{-1} A_EU z_U.
+// Per element the factors S^{-1} (NV x NV), G = A_UE (NU x NE),
+// H = D^{-1} A_EU (NE x NU) and d = D^{-1} (NE) are stored, in FP32 and
+// element fastest (number k of element e at F[k * n + e]): 2540 numbers at P3
+// on triangles against 4900 for the whole inverse, from a 30-row inversion
+// instead of a 70-row one.  FP32 for both state precisions: the
+// preconditioner only steers GMRES (the Krylov residual uses the exact
+// Jacobian) and its apply reads half the bytes.  A_EE's off-diagonal entries
+// are quadrature rounding of zero (about 1e-13 of the diagonal) and are not
+// read.
+template <int D, int P>
+struct Schur {
+  static constexpr int NP = Shape<D, P>::NP;
+  static constexpr int BS = Shape<D, P>::BS;
+  static constexpr int NV = (1 + D) * NP;  // depth and velocity rows
+  static constexpr int NU = D * NP;        // velocity rows, NP .. NV - 1
+  static constexpr int NE = D * D * NP;    // stress rows, NV .. BS - 1
+  static constexpr int OS = 0;             // S^{-1}, row-major
+  static constexpr int OG = NV * NV;       // G = A_UE, row-major
+  static constexpr int OH = OG + NU * NE;  // H = D^{-1} A_EU, row-major
+  static constexpr int OD = OH + NE * NU;  // d = D^{-1}
+  static constexpr int NB = OD + NE;       // numbers per element
+  static_assert(NV <= 64, "the Schur complement rows must fit one wave");
+};
+// numbers per element of the stored factors (host side)
+constexpr int schur_numbers(int dim, int np) {
+  return ((1 + dim) * np) * ((1 + dim) * np) + 2 * (dim * np) * (dim * dim * np) + dim * dim * np;
+}
 
 // the device library's wave reduction of 64-bit keys (its 32-bit siblings are
 // declared by the HIP headers)
@@ -748,13 +771,11 @@ template <class T> struct PivotKey;
 template <> struct PivotKey<double> {
   using U = unsigned long long;
   static __device__ __forceinline__ U bits(double v) { return (U)__double_as_longlong(v); }
-  static __device__ __forceinline__ double value(U k) { return __longlong_as_double((long long)k); }
   static __device__ __forceinline__ U wave_max(U k) { return __ockl_wfred_max_u64(k); }
 };
 template <> struct PivotKey<float> {
   using U = unsigned int;
   static __device__ __forceinline__ U bits(float v) { return (U)__float_as_uint(v); }
-  static __device__ __forceinline__ float value(U k) { return __uint_as_float(k); }
   static __device__ __forceinline__ U wave_max(U k) { return __ockl_wfred_max_u32(k); }
 };
 
@@ -769,116 +790,161 @@ __device__ __forceinline__ double lane_value(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <int BS, class T>
-__device__ __forceinline__ void block_inverse_elem(const T* __restrict__ A, float* __restrict__ Ainv, int n, int e) {
-  constexpr int NT = inv_threads<BS>();
-  constexpr int NW = NT / 64;
-  // per-wave pivot candidates (value, row, the row itself), double-buffered
-  // by step parity so that one barrier per step suffices
-  __shared__ T crow[2][NW][BS];
-  __shared__ T cval[2][NW];
-  __shared__ int cidx[2][NW];
-  __shared__ int piv[BS];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const bool own = t < BS;
-  const T* src = A + (size_t)e * BS * BS + (size_t)(own ? t : 0) * BS;
-  T r[BS];
+// The factors of element e from its diagonal block A (row-major, [e][row][col])
+// by one wave.  Lane t < NV holds row t of S in registers: the row of A_VV,
+// minus (velocity rows) the products of its A_UE entries with the rows of
+// D^{-1} A_EU, which are wave-uniform and read as scalars.  S is inverted by
+// Gauss-Jordan elimination with partial pivoting on [S | I], in place and
+// without row swaps: at step k the lane whose row has the largest |entry| in
+// the current column among the rows not yet used (lowest row on ties)
+// supplies the pivot row, which the other lanes read from its registers
+// lane by lane.  The register row is rotated by one position per step, so
+// the current column is always position 0 and every step runs the same code:
+// position j takes the updated entry of position j + 1 and the last position
+// the new column of the right-hand part.  Pivot rows are not normalised when
+// chosen; each lane divides its row by its own pivot at the end, which
+// commutes with the later eliminations.  After NV steps the lane that
+// supplied pivot k holds row k of S^{-1}, its position j the column of the
+// row that supplied pivot j.
+template <int D, int P, class T>
+__device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float* __restrict__ F, int n, int e) {
+  using Z = Schur<D, P>;
+  const int lane = threadIdx.x & 63;
+  const T* blk = A + (size_t)e * Z::BS * Z::BS;
+  float* out = F + e;
+  // d and H, spread over the lanes
+  for (int i = lane; i < Z::NE; i += 64)
+    out[(size_t)(Z::OD + i) * n] = (float)(T(1) / blk[(size_t)(Z::NV + i) * Z::BS + Z::NV + i]);
+  for (int i = lane; i < Z::NE * Z::NU; i += 64) {
+    const T* ek = blk + (size_t)(Z::NV + i / Z::NU) * Z::BS;
+    out[(size_t)(Z::OH + i) * n] = (float)(ek[Z::NP + i % Z::NU] / ek[Z::NV + i / Z::NU]);
+  }
+  const bool own = lane < Z::NV;
+  const bool vel = own && lane >= Z::NP;
+  const T* row = blk + (size_t)(own ? lane : 0) * Z::BS;
+  T r[Z::NV];
 #pragma unroll
-  for (int j = 0; j < BS; ++j) r[j] = own ? src[j] : T(0);
+  for (int c = 0; c < Z::NV; ++c) r[c] = own ? row[c] : T(0);
+  float* gout = out + (size_t)(Z::OG + (vel ? lane - Z::NP : 0) * Z::NE) * n;
+#pragma unroll 2
+  for (int k = 0; k < Z::NE; ++k) {
+    const T* ek = blk + (size_t)(Z::NV + k) * Z::BS;  // stress row k: wave-uniform
+    const T gk = vel ? row[Z::NV + k] : T(0);
+    if (vel) gout[(size_t)k * n] = (float)gk;
+    const T f = gk / ek[Z::NV + k];
+#pragma unroll
+    for (int c = 0; c < Z::NU; ++c) r[Z::NP + c] -= f * ek[Z::NP + c];
+  }
   bool used = !own;
-  int myk = 0;
+  int myk = 0, pv = 0;
   T dp = T(1);  // the lane's own pivot value
-  for (int k = 0; k < BS; ++k) {
-    const int buf = k & 1;
-    // the wave's pivot candidate: largest |entry| among its rows not yet used,
-    // lowest row on ties, as two wave reductions on an integer key (the bits
-    // of a non-negative float order like its value; used rows key 0).  A NaN
-    // entry counts as the largest, so the pivot is always a row not yet used
-    // (every row is used exactly once and piv[] stays a permutation).
+  for (int k = 0; k < Z::NV; ++k) {
+    // pivot: largest |entry| among the rows not yet used, lowest row on ties,
+    // as two wave reductions on an integer key (used rows key 0).  A NaN entry
+    // counts as the largest, so every row is used exactly once.
     T av = fabs(r[0]);
     if (av != av) av = T(INFINITY);
     using K = typename PivotKey<T>::U;
     const K key = used ? K(0) : PivotKey<T>::bits(av) + K(1);
     const K mx = PivotKey<T>::wave_max(key);
-    int bi = (int)__ockl_wfred_min_u32(key == mx ? (unsigned)t : 0xffffffffu);
-    T best = mx == K(0) ? T(-1) : PivotKey<T>::value(mx - K(1));
-    if constexpr (NW == 1) {
-      // one wave: the pivot row is read from the pivot lane's registers into
-      // scalar registers (no LDS traffic and no barrier per step)
-      bi = __builtin_amdgcn_readfirstlane(bi);
-      const bool me = t == bi;
-      const T d = lane_value(r[0], bi);
-      if (me) { used = true; myk = k; dp = d; }
-      if (t == 0) piv[k] = bi;
-      const T f = me ? T(0) : r[0] / d;
+    const int bi = __builtin_amdgcn_readfirstlane((int)__ockl_wfred_min_u32(key == mx ? (unsigned)lane : 0xffffffffu));
+    const bool me = lane == bi;
+    const T dv = lane_value(r[0], bi);
+    if (me) { used = true; myk = k; dp = dv; }
+    if (lane == k) pv = bi;
+    const T f = me ? T(0) : r[0] / dv;
 #pragma unroll
-      for (int j = 0; j + 1 < BS; ++j) r[j] = r[j + 1] - f * lane_value(r[j + 1], bi);
-      r[BS - 1] = me ? T(1) : -f;
-    } else {
-      if (t == bi) {
-#pragma unroll
-        for (int j = 0; j < BS; ++j) crow[buf][wv][j] = r[j];
-      }
-      if (lane == 0) { cval[buf][wv] = best; cidx[buf][wv] = bi; }
-      __syncthreads();
-      int w = 0;
-      best = cval[buf][0];
-      bi = cidx[buf][0];
-#pragma unroll
-      for (int u = 1; u < NW; ++u)
-        if (cval[buf][u] > best || (cval[buf][u] == best && cidx[buf][u] < bi)) { best = cval[buf][u]; bi = cidx[buf][u]; w = u; }
-      const T* prow = crow[buf][w];
-      const bool me = t == bi;
-      if (me) { used = true; myk = k; dp = prow[0]; }
-      if (t == 0) piv[k] = bi;
-      const T f = me ? T(0) : r[0] / prow[0];
-#pragma unroll
-      for (int j = 0; j + 1 < BS; ++j) r[j] = r[j + 1] - f * prow[j + 1];
-      r[BS - 1] = me ? T(1) : -f;
-    }
+    for (int j = 0; j + 1 < Z::NV; ++j) r[j] = r[j + 1] - f * lane_value(r[j + 1], bi);
+    r[Z::NV - 1] = me ? T(1) : -f;
   }
-  __syncthreads();
   if (own) {
     const T s = T(1) / dp;
-    float* dst = Ainv + (size_t)myk * BS * n + e;
+    float* srow = out + (size_t)(Z::OS + myk * Z::NV) * n;
 #pragma unroll
-    for (int j = 0; j < BS; ++j) dst[(size_t)piv[j] * n] = (float)(r[j] * s);
+    for (int j = 0; j < Z::NV; ++j) srow[(size_t)__builtin_amdgcn_readlane(pv, j) * n] = (float)(r[j] * s);
   }
 }
 
-template <int BS, class T>
-__global__ void __launch_bounds__(inv_threads<BS>(), (inv_waves<BS, T>())) k_block_inverse(const T* __restrict__ A, float* __restrict__ Ainv,
-                                                                     int n) {
-  block_inverse_elem<BS, T>(A, Ainv, n, xcd_tile(blockIdx.x, gridDim.x));
+// four elements per workgroup, one per wave; consecutive elements run on one
+// XCD, so the elements that share a line of the output fill it in one L2
+constexpr int kSchurEPB = 4;
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) k_schur_build(const T* __restrict__ A, float* __restrict__ F, int n) {
+  const int e = xcd_tile(blockIdx.x, gridDim.x) * kSchurEPB + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (e < n) schur_build_elem<D, P, T>(A, F, n, e);
 }
 
-// y = blockdiag(A_e)^{-1} x: one lane per (row, element), element fastest.
-// A launch tile is 256 elements of one row, and consecutive tiles take the
-// rows of the same elements (tile t: row t % BS, elements (t / BS) * 256 +
-// lane), so the BS rows of an element tile reuse its slice of x from the L2
-// of one XCD instead of refetching it from HBM for every row.
-template <int BS>
-__device__ __forceinline__ void row_tile(int t, int& row, int& e) {
-  row = t % BS;
-  e = (t / BS) * 256 + (int)threadIdx.x;
-}
-
-template <int BS, class T>
-__device__ __forceinline__ void block_apply_item(const float* __restrict__ Ainv, const T* __restrict__ x,
-                                                 T* __restrict__ y, int n, int row, int e) {
-  const float* arow = Ainv + (size_t)row * BS * n + e;
-  T s = T(0);
+// Block solve of 64 consecutive elements by a workgroup of four waves, one
+// lane per element.  x is staged in LDS (the stress rows already scaled by
+// D^{-1}); then r_U = x_U - G t_E replaces x_U, z_V = S^{-1} r_V is written
+// and z_U replaces r_U, and z_E = t_E - H z_U is written.  The waves take the
+// rows of each phase in turn.  Every factor row is a coalesced read of 64
+// consecutive FP32 numbers.  scale() (called once by every thread, after the
+// first phase) gives the factor applied to the written z.
+constexpr int kPrecEB = 64;
+template <int D, int P, class T, class Scale>
+__device__ __forceinline__ void schur_apply_tile(const float* __restrict__ F, const T* __restrict__ x,
+                                                 T* __restrict__ y, int n, int e0, Scale scale) {
+  using Z = Schur<D, P>;
+  constexpr int NW = 4;
+  __shared__ double xs[Z::BS][kPrecEB];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const unsigned e = (unsigned)(e0 + lane);
+  const bool live = (int)e < n;
+  auto ld = [&](int k) -> double { return (double)rowld(F, k, n, e); };
+  for (int r = w; r < Z::BS; r += NW) {
+    double v = 0.0;
+    if (live) {
+      v = (double)rowld(x, r, n, e);
+      if (r >= Z::NV) v *= ld(Z::OD + r - Z::NV);
+    }
+    xs[r][lane] = v;
+  }
+  __syncthreads();
+  for (int u = w; u < Z::NU; u += NW) {
+    double s = xs[Z::NP + u][lane];
+    if (live) {
 #pragma unroll
-  for (int j = 0; j < BS; ++j) s += (T)arow[(size_t)j * n] * x[(size_t)j * n + e];
-  y[(size_t)row * n + e] = s;
+      for (int k = 0; k < Z::NE; ++k) s -= ld(Z::OG + u * Z::NE + k) * xs[Z::NV + k][lane];
+    }
+    xs[Z::NP + u][lane] = s;
+  }
+  __syncthreads();
+  const double sg = scale();
+  constexpr int NVW = (Z::NV + NW - 1) / NW;
+  double z[NVW];
+#pragma unroll
+  for (int i = 0; i < NVW; ++i) {
+    const int v = w + NW * i;
+    double s = 0.0;
+    if (v < Z::NV && live) {
+#pragma unroll
+      for (int c = 0; c < Z::NV; ++c) s += ld(Z::OS + v * Z::NV + c) * xs[c][lane];
+      rowref(y, v, n, e) = (T)(sg * s);
+    }
+    z[i] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NVW; ++i) {
+    const int v = w + NW * i;
+    if (v >= Z::NP && v < Z::NV) xs[v][lane] = z[i];
+  }
+  __syncthreads();
+  if (!live) return;
+  for (int k = w; k < Z::NE; k += NW) {
+    double s = xs[Z::NV + k][lane];
+#pragma unroll
+    for (int c = 0; c < Z::NU; ++c) s -= ld(Z::OH + k * Z::NU + c) * xs[Z::NP + c][lane];
+    rowref(y, Z::NV + k, n, e) = (T)(sg * s);
+  }
 }
 
-template <int BS, class T>
-__global__ void __launch_bounds__(256) k_block_apply(const float* __restrict__ Ainv, const T* __restrict__ x,
+template <int D, int P, class T>
+__global__ void __launch_bounds__(256) k_schur_apply(const float* __restrict__ F, const T* __restrict__ x,
                                                       T* __restrict__ y, int n) {
-  int row, e;
-  row_tile<BS>(xcd_tile(blockIdx.x, gridDim.x), row, e);
-  if (e < n) block_apply_item<BS, T>(Ainv, x, y, n, row, e);
+  schur_apply_tile<D, P, T>(F, x, y, n, (int)blockIdx.x * kPrecEB, [] { return 1.0; });
 }
 
 // per-element contributions to the mass, the active (yielded) area, the

@@ -81,7 +81,7 @@ struct bsw_disc_s {
   const void* lin_W = nullptr;
   bsw_params lin_prm{};
   double lin_dt = 0.0;
-  void* blocks = nullptr;      // block inverses (FP32), [row][col][n_el]
+  void* blocks = nullptr;      // block-Jacobi factors (FP32), [number][n_el]
   void* blocks_raw = nullptr;  // unfactored blocks, [n_el][row][col]
   // face traces (field values at every face point) of the linearisation state
   void* trL = nullptr;
@@ -571,8 +571,8 @@ struct LinearizeLaunch {
                        (const T*)d->trL, (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt,
                                                                             (const T*)d->dirtab));
     HIPCHK(c, hipGetLastError());
-    hipLaunchKernelGGL((k_block_inverse<S::BS, T>), dim3(m.n_el), dim3(inv_threads<S::BS>()), 0, c->stream,
-                       (const T*)d->blocks_raw, (float*)d->blocks, m.n_el);
+    hipLaunchKernelGGL((k_schur_build<D, P, T>), dim3((unsigned)((m.n_el + kSchurEPB - 1) / kSchurEPB)), dim3(256), 0,
+                       c->stream, (const T*)d->blocks_raw, (float*)d->blocks, m.n_el);
     HIPCHK(c, hipGetLastError());
     return BSW_OK;
   }
@@ -582,9 +582,8 @@ struct PrecLaunch {
   bsw_disc d; const void* x; void* y;
   template <int D, int P, class T>
   int operator()() {
-    using S = Shape<D, P>;
     auto m = view<T>(d);
-    hipLaunchKernelGGL((k_block_apply<S::BS, T>), dim3((unsigned)(S::BS * ((m.n_el + 255) / 256))), dim3(256), 0,
+    hipLaunchKernelGGL((k_schur_apply<D, P, T>), dim3((unsigned)((m.n_el + kPrecEB - 1) / kPrecEB)), dim3(256), 0,
                        d->mesh->ctx->stream, (const float*)d->blocks, (const T*)x, (T*)y, m.n_el);
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
@@ -1043,8 +1042,9 @@ int bsw_jacobian_linearize(bsw_disc d, const bsw_params* p, double dt, const voi
   if (int rc = check_params(d, p)) return rc;
   bsw_ctx c = d->mesh->ctx;
   const size_t nb = (size_t)d->bs * d->bs * d->mesh->n_el;
+  const size_t nf = (size_t)schur_numbers(d->mesh->dim, d->ref.np) * d->mesh->n_el;
   if (!d->blocks) {
-    if (hipMalloc(&d->blocks, nb * sizeof(float)) != hipSuccess || hipMalloc(&d->blocks_raw, nb * d->wsize) != hipSuccess)
+    if (hipMalloc(&d->blocks, nf * sizeof(float)) != hipSuccess || hipMalloc(&d->blocks_raw, nb * d->wsize) != hipSuccess)
       return fail(c, BSW_E_OOM, "block-Jacobi storage");
   }
   d->lin_W = W;

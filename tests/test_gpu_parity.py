@@ -107,16 +107,35 @@ def test_jacobian_apply_blocks_and_preconditioner(ctx, dim, P, n, reg):
     Bg = pr.host(pr.disc.jacobian_blocks())
     Bo = pr.orc.jac_blocks(p, W, dt)
     assert np.abs(Bg - Bo).max() <= 1e-12 * np.abs(Bo).max()
-    # preconditioner: the block inverses are stored in FP32, so y_e is the
-    # exact block solve up to the rounding of each inverse entry:
-    # |y - B^{-1} x| <= 2^-24 |B^{-1}| |x| (+ FP64 inversion error)
+    # preconditioner: the exact block solve y_e = B_e^{-1} x_e, taken through
+    # the Schur complement S = A_VV - A_VE D^{-1} A_EV of the stress block
+    # D = A_EE (diagonal), with the factors S^{-1}, G = A_UE, H = D^{-1} A_EU
+    # and d = D^{-1} stored in FP32.  First-order bound of the rounding of
+    # those factors (u = 2^-24) through
+    #   t = d x_E, r_U = x_U - G t, z_V = S^{-1} r_V, z_E = t - H z_U,
+    # doubled, plus the FP64 inversion error:
     yp = pr.host(pr.disc.precond_apply(pr.dev(x)))
     nf, np_, ne = pr.shape
     xe = np.transpose(x, (2, 0, 1)).reshape(ne, nf * np_)
     ye = np.transpose(yp, (2, 0, 1)).reshape(ne, nf * np_)
-    Binv = np.linalg.inv(Bo)
-    ex = np.einsum("eij,ej->ei", Binv, xe)
-    bound = 2.0 ** -23 * np.einsum("eij,ej->ei", np.abs(Binv), np.abs(xe)) + 1e-9 * np.abs(ex).max()
+    ex = np.einsum("eij,ej->ei", np.linalg.inv(Bo), xe)
+    nv = (1 + dim) * np_
+    u = 2.0 ** -24
+    G = Bo[:, np_:nv, nv:]
+    d = 1.0 / np.einsum("eii->ei", Bo[:, nv:, nv:])
+    H = d[:, :, None] * Bo[:, nv:, np_:nv]
+    S = Bo[:, :nv, :nv].copy()
+    S[:, np_:, np_:] -= G @ H
+    aS, aG, aH = np.abs(np.linalg.inv(S)), np.abs(G), np.abs(H)
+    at = np.abs(d * xe[:, nv:])
+    ar = np.abs(xe[:, :nv])
+    ar[:, np_:] += np.einsum("eij,ej->ei", aG, at)
+    dr = np.zeros_like(ar)
+    dr[:, np_:] = 2 * u * np.einsum("eij,ej->ei", aG, at)
+    dzv = u * np.einsum("eij,ej->ei", aS, ar) + np.einsum("eij,ej->ei", aS, dr)
+    azu = np.einsum("eij,ej->ei", aS, ar)[:, np_:]
+    dze = u * at + u * np.einsum("eij,ej->ei", aH, azu) + np.einsum("eij,ej->ei", aH, dzv[:, np_:])
+    bound = 2 * np.concatenate([dzv, dze], axis=1) + 1e-9 * np.abs(ex).max()
     assert np.all(np.abs(ye - ex) <= bound)
     # and not much looser than that: the rounding is visible but small
     assert np.abs(ye - ex).max() <= 1e-5 * np.abs(ex).max()

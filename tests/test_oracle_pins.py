@@ -210,3 +210,46 @@ def test_c1_newton_record(oracle_mod):
     m0 = orc.diagnostics(pb.params, W0)["mass"]
     assert abs(orc.diagnostics(pb.params, W40)["mass"] - m0) < 1e-13 * m0
     assert abs(orc.diagnostics(pb.params, W10)["mass"] - m0) < 1e-13 * m0
+
+
+@pytest.mark.parametrize("dim,P", [(1, 2), (2, 1), (2, 3)])
+@pytest.mark.parametrize("reg", [1, 3])
+def test_jacobian_block_structure(oracle_mod, dim, P, reg):
+    """The diagonal Jacobian blocks have the structure the block-Jacobi
+    preconditioner's Schur form relies on (Sec. 3, the mixed form of the
+    strain rate): the stress rows' own block is the element mass matrix
+    |J| I of the orthonormal basis (|J| = length / 2 on an interval, twice
+    the area on a triangle, measured here from the vertices), the depth rows
+    do not involve E and the stress rows do not involve h.  The Schur
+    complement solve then equals the direct block solve."""
+    xy, e2v = wl.mesh_1d(7) if dim == 1 else wl.mesh_tri(3)
+    orc = oracle_mod.Oracle(dim, P, xy, e2v)
+    p = wl.Params(alpha=0.12, eta=0.8, sigma0=40.0, gamma=1e3, beta=1e3, reg=reg)
+    W = wl.random_state(dim, P, orc.n_el, 11)
+    B = orc.jac_blocks(p, W, 0.02)
+    npm = wl.n_modes(dim, P)
+    nv = (1 + dim) * npm
+    if dim == 1:
+        detJ = 0.5 * np.abs(xy[e2v[:, 1], 0] - xy[e2v[:, 0], 0])
+    else:
+        a, b, c = xy[e2v[:, 0]], xy[e2v[:, 1]], xy[e2v[:, 2]]
+        detJ = np.abs((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]))
+    ne = B.shape[1] - nv
+    AEE = B[:, nv:, nv:]
+    assert np.abs(AEE - detJ[:, None, None] * np.eye(ne)).max() <= 1e-12 * detJ.max()
+    assert np.all(B[:, :npm, nv:] == 0.0) and np.all(B[:, nv:, :npm] == 0.0)
+    # and the velocity-stress couplings are there (the Schur correction is not empty)
+    assert np.abs(B[:, npm:nv, nv:]).max() > 0.1 and np.abs(B[:, nv:, npm:nv]).max() > 0.1
+    x = wl.rng_for(11, 1).standard_normal((orc.n_el, B.shape[1]))
+    direct = np.linalg.solve(B, x[..., None])[..., 0]
+    d = 1.0 / detJ
+    G = B[:, npm:nv, nv:]
+    H = d[:, None, None] * B[:, nv:, npm:nv]
+    S = B[:, :nv, :nv].copy()
+    S[:, npm:, npm:] -= G @ H
+    t = d[:, None] * x[:, nv:]
+    r = x[:, :nv].copy()
+    r[:, npm:] -= np.einsum("eij,ej->ei", G, t)
+    zv = np.linalg.solve(S, r[..., None])[..., 0]
+    ze = t - np.einsum("eij,ej->ei", H, zv[:, npm:])
+    assert np.abs(np.concatenate([zv, ze], 1) - direct).max() <= 1e-10 * np.abs(direct).max()
