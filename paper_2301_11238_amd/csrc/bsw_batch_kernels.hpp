@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) kb_schur_build(const InstDesc<T>* __restr
   const int ai = bset_find(A, b);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int e = (b - A.tile0[ai]) * kSchurEPB + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  if (e < I.m.n_el) schur_build_elem<D, P, T>(I.blk_raw, I.blk, I.m.n_el, e);
+  schur_build_elem<D, P, T>(I.blk_raw, I.blk, I.m.n_el, e, e < I.m.n_el);
 }
 
 // y = M^{-1} x on Krylov slot j, 64 elements per workgroup (k_schur_apply)

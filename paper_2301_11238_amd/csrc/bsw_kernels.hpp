@@ -791,50 +791,80 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 }
 
 // The factors of element e from its diagonal block A (row-major, [e][row][col])
-// by one wave.  Lane t < NV holds row t of S in registers: the row of A_VV,
-// minus (velocity rows) the products of its A_UE entries with the rows of
-// D^{-1} A_EU, which are wave-uniform and read as scalars.  S is inverted by
-// Gauss-Jordan elimination with partial pivoting on [S | I], in place and
-// without row swaps: at step k the lane whose row has the largest |entry| in
-// the current column among the rows not yet used (lowest row on ties)
-// supplies the pivot row, which the other lanes read from its registers
-// lane by lane.  The register row is rotated by one position per step, so
-// the current column is always position 0 and every step runs the same code:
-// position j takes the updated entry of position j + 1 and the last position
-// the new column of the right-hand part.  Pivot rows are not normalised when
-// chosen; each lane divides its row by its own pivot at the end, which
-// commutes with the later eliminations.  After NV steps the lane that
-// supplied pivot k holds row k of S^{-1}, its position j the column of the
-// row that supplied pivot j.
+// by one wave of a four-wave workgroup (every wave reaches the barrier; live
+// is false for a wave past the last element, whose loads then read element
+// 0's block and whose results are dropped).  D^{-1} goes to the wave's slice
+// of LDS; D^{-1} A_EU is formed and stored by all lanes.  Lane t < NV holds
+// row t of S in registers: the row of A_VV, minus (velocity rows) the
+// products of its A_UE entries, scaled by D^{-1}, with the rows of A_EU, which
+// are wave-uniform and read as scalars.  The loads of each phase go out
+// together, before their first use.  S is inverted by Gauss-Jordan
+// elimination with partial pivoting on [S | I], in place and without row
+// swaps: at step k the lane whose row has the largest |entry| in the current
+// column among the rows not yet used (lowest row on ties) supplies the pivot
+// row, which the other lanes read from its registers lane by lane.  The
+// register row is rotated by one position per step, so the current column is
+// always position 0 and every step runs the same code: position j takes the
+// updated entry of position j + 1 and the last position the new column of the
+// right-hand part.  Pivot rows are not normalised when chosen; each lane
+// divides its row by its own pivot at the end, which commutes with the later
+// eliminations.  After NV steps the lane that supplied pivot k holds row k of
+// S^{-1}, its position j the column of the row that supplied pivot j.
+constexpr int kSchurEPB = 4;  // elements (waves) per workgroup
 template <int D, int P, class T>
-__device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float* __restrict__ F, int n, int e) {
+__device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float* __restrict__ F, int n, int e,
+                                                 bool live) {
   using Z = Schur<D, P>;
+  constexpr int NH = Z::NE * Z::NU;
+  constexpr int JH = (NH + 63) / 64;  // entries of D^{-1} A_EU per lane
+  constexpr int KC = Z::NE % 20 == 0 ? 20 : (Z::NE % 8 == 0 ? 8 : Z::NE);  // A_UE entries per batch
+  __shared__ T sD[kSchurEPB][Z::NE];
   const int lane = threadIdx.x & 63;
-  const T* blk = A + (size_t)e * Z::BS * Z::BS;
-  float* out = F + e;
-  // d and H, spread over the lanes
-  for (int i = lane; i < Z::NE; i += 64)
-    out[(size_t)(Z::OD + i) * n] = (float)(T(1) / blk[(size_t)(Z::NV + i) * Z::BS + Z::NV + i]);
-  for (int i = lane; i < Z::NE * Z::NU; i += 64) {
-    const T* ek = blk + (size_t)(Z::NV + i / Z::NU) * Z::BS;
-    out[(size_t)(Z::OH + i) * n] = (float)(ek[Z::NP + i % Z::NU] / ek[Z::NV + i / Z::NU]);
-  }
-  const bool own = lane < Z::NV;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const T* blk = A + (size_t)(live ? e : 0) * Z::BS * Z::BS;
+  float* out = F + (live ? e : 0);
+  const bool own = live && lane < Z::NV;
   const bool vel = own && lane >= Z::NP;
-  const T* row = blk + (size_t)(own ? lane : 0) * Z::BS;
+  const T* row = blk + (size_t)(lane < Z::NV ? lane : 0) * Z::BS;
+  T a[JH];
+#pragma unroll
+  for (int j = 0; j < JH; ++j) {
+    const int i = lane + 64 * j < NH ? lane + 64 * j : 0;
+    a[j] = blk[(size_t)(Z::NV + i / Z::NU) * Z::BS + Z::NP + i % Z::NU];
+  }
+  const int kd = lane < Z::NE ? lane : 0;
+  const T dd = blk[(size_t)(Z::NV + kd) * Z::BS + Z::NV + kd];
   T r[Z::NV];
 #pragma unroll
-  for (int c = 0; c < Z::NV; ++c) r[c] = own ? row[c] : T(0);
-  float* gout = out + (size_t)(Z::OG + (vel ? lane - Z::NP : 0) * Z::NE) * n;
-#pragma unroll 2
-  for (int k = 0; k < Z::NE; ++k) {
-    const T* ek = blk + (size_t)(Z::NV + k) * Z::BS;  // stress row k: wave-uniform
-    const T gk = vel ? row[Z::NV + k] : T(0);
-    if (vel) gout[(size_t)k * n] = (float)gk;
-    const T f = gk / ek[Z::NV + k];
-#pragma unroll
-    for (int c = 0; c < Z::NU; ++c) r[Z::NP + c] -= f * ek[Z::NP + c];
+  for (int c = 0; c < Z::NV; ++c) r[c] = row[c];
+  if (lane < Z::NE) {
+    const T di = T(1) / dd;
+    sD[w][lane] = di;
+    if (live) out[(size_t)(Z::OD + lane) * n] = (float)di;
   }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < JH; ++j) {
+    const int i = lane + 64 * j;
+    if (live && i < NH) out[(size_t)(Z::OH + i) * n] = (float)(a[j] * sD[w][i / Z::NU]);
+  }
+  float* gout = out + (size_t)(Z::OG + (vel ? lane - Z::NP : 0) * Z::NE) * n;
+#pragma unroll 1
+  for (int k0 = 0; k0 < Z::NE; k0 += KC) {
+    T g[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) g[kk] = row[Z::NV + k0 + kk];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int k = k0 + kk;
+      if (vel) gout[(size_t)k * n] = (float)g[kk];
+      const T f = vel ? g[kk] * sD[w][k] : T(0);
+      const T* ek = blk + (size_t)(Z::NV + k) * Z::BS + Z::NP;  // stress row k: wave-uniform
+#pragma unroll
+      for (int c = 0; c < Z::NU; ++c) r[Z::NP + c] -= f * ek[c];
+    }
+  }
+  if (!live) return;
   bool used = !own;
   int myk = 0, pv = 0;
   T dp = T(1);  // the lane's own pivot value
@@ -865,13 +895,12 @@ __device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float*
   }
 }
 
-// four elements per workgroup, one per wave; consecutive elements run on one
-// XCD, so the elements that share a line of the output fill it in one L2
-constexpr int kSchurEPB = 4;
+// consecutive elements run on one XCD, so the elements that share a line of
+// the output fill it in one L2
 template <int D, int P, class T>
 __global__ void __launch_bounds__(256) k_schur_build(const T* __restrict__ A, float* __restrict__ F, int n) {
   const int e = xcd_tile(blockIdx.x, gridDim.x) * kSchurEPB + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  if (e < n) schur_build_elem<D, P, T>(A, F, n, e);
+  schur_build_elem<D, P, T>(A, F, n, e, e < n);
 }
 
 // Block solve of 64 consecutive elements by a workgroup of four waves, one
