@@ -325,7 +325,8 @@ int bsw_solve(bsw_disc disc, const bsw_params* prm, const bsw_solve_opts* opts, 
  * class floor(log2 of the launch's element count)) the library times the
  * first launches of every variant (HIP events, read without blocking) and
  * keeps the fastest for the process.  The single-call entry points
- * (bsw_operator_apply, bsw_jacobian_apply) use variant 1.
+ * (bsw_operator_apply, bsw_jacobian_apply) use the variant the policy
+ * forces, else variant 1.
  * bsw_tile_policy: -1 autotune (default), 0/1/2 force a variant;
  * *previous (may be NULL) receives the old policy.  Process-wide. */
 int bsw_tile_policy(int policy, int* previous);

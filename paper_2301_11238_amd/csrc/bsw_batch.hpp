@@ -125,6 +125,12 @@ TileTuner& tile_tuner() {
   return t;
 }
 
+int single_call_variant() {
+  TileTuner& t = tile_tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  return t.policy;
+}
+
 // Device bytes one resident instance takes: state and Krylov vectors,
 // diagonal blocks and their FP32 block-Jacobi factors, face traces, reduction
 // partials, mesh.

@@ -135,14 +135,27 @@ __global__ void __launch_bounds__(256) kb_jac_columns(const InstDesc<T>* __restr
   jac_columns_elem<D, P, T>(bslot(I, sW, 0), I.trL, I.blk_raw, I.m, I.p, blockIdx.x - A.tile0[ai]);
 }
 
+// a pointer the whole wave holds, moved to scalar registers (so that the
+// compiler treats loads through it at uniform offsets as scalar loads)
+template <class Q>
+__device__ __forceinline__ Q* wave_uniform(Q* q) {
+  const uint64_t u = (uint64_t)(uintptr_t)q;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return (Q*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 // block-Jacobi factors, four elements per workgroup (k_schur_build)
 template <int D, int P, class T>
 __global__ void __launch_bounds__(256) kb_schur_build(const InstDesc<T>* __restrict__ ds, BatchSet A) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int ai = bset_find(A, b);
   const InstDesc<T> I = ds[A.inst[ai]];
-  const int e = (b - A.tile0[ai]) * kSchurEPB + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  schur_build_elem<D, P, T>(I.blk_raw, I.blk, I.m.n_el, e, e < I.m.n_el);
+  const int n = __builtin_amdgcn_readfirstlane(I.m.n_el);
+  // (the instance search runs in vector registers: the element index is
+  // made wave-uniform explicitly)
+  const int e = __builtin_amdgcn_readfirstlane((b - A.tile0[ai]) * kSchurEPB + ((int)threadIdx.x >> 6));
+  schur_build_elem<D, P, T>(wave_uniform(I.blk_raw), wave_uniform(I.blk), n, e, e < n);
 }
 
 // y = M^{-1} x on Krylov slot j, 64 elements per workgroup (k_schur_apply)

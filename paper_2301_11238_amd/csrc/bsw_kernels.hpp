@@ -859,7 +859,12 @@ __device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float*
       const int k = k0 + kk;
       if (vel) gout[(size_t)k * n] = (float)g[kk];
       const T f = vel ? g[kk] * sD[w][k] : T(0);
-      const T* ek = blk + (size_t)(Z::NV + k) * Z::BS + Z::NP;  // stress row k: wave-uniform
+      // stress row k: wave-uniform, read through the constant address space
+      // (the block is not written by this kernel), which makes them scalar
+      // loads also where the compiler cannot prove that the factor stores do
+      // not alias the block
+      const __attribute__((address_space(4))) T* ek =
+          (const __attribute__((address_space(4))) T*)(blk + (size_t)(Z::NV + k) * Z::BS + Z::NP);
 #pragma unroll
       for (int c = 0; c < Z::NU; ++c) r[Z::NP + c] -= f * ek[c];
     }

@@ -508,17 +508,29 @@ int finish(bsw_disc d, int nblk, int nv, const int* ops, double* host_out) {
 }
 
 // --------------------------------------------------------------- kernel launchers
+// the element-pass variant the single-call entry points launch: the one
+// bsw_tile_policy forces, else variant 1 (defined with the autotuner)
+int single_call_variant();
+
 struct OpLaunch {
   bsw_disc d; const bsw_params* p; double dt; const void* W; const void* bold; void* R;
+  template <int D, int P, class T, int V>
+  void launch(hipStream_t st, const MeshView<T>& m, const DevParams<T>& prm) {
+    hipLaunchKernelGGL((k_elem<D, P, T, 0, V>), grid1(m.n_el, etile_eb<D, P, V>()), dim3(etile_nt<D, V>()), 0, st,
+                       (const T*)W, (const T*)nullptr, (const T*)bold, (T*)R, (const T*)nullptr, m, prm);
+  }
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
     hipStream_t st = d->mesh->ctx->stream;
     if (int rc = sync_dirtab<T>(d, *p)) return rc;
     // one element pass: it evaluates the neighbours' side of W itself
-    hipLaunchKernelGGL((k_elem<D, P, T, 0, 1>), grid1(m.n_el, etile_eb<D, P, 1>()), dim3(etile_nt<D, 1>()), 0, st, (const T*)W,
-                       (const T*)nullptr, (const T*)bold, (T*)R, (const T*)nullptr, m,
-                       devparams<T>(*p, dt, (const T*)d->dirtab));
+    const auto prm = devparams<T>(*p, dt, (const T*)d->dirtab);
+    switch (single_call_variant()) {
+      case 0: launch<D, P, T, 0>(st, m, prm); break;
+      case 2: launch<D, P, T, 2>(st, m, prm); break;
+      default: launch<D, P, T, 1>(st, m, prm);
+    }
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
@@ -541,16 +553,23 @@ struct JacApplyLaunch {
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional: timestamps of this dispatch
   // one element pass (it evaluates the neighbours' side of x itself); with
   // events, ev_start and ev_stop stamp its start and end
+  template <int D, int P, class T, int V>
+  void launch(hipStream_t st, const MeshView<T>& m, const DevParams<T>& prm) {
+    hipExtLaunchKernelGGL((k_elem<D, P, T, 1, V>), grid1(m.n_el, etile_eb<D, P, V>()), dim3(etile_nt<D, V>()), 0, st,
+                          ev_start, ev_stop, 0, (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y,
+                          (const T*)d->trL, m, prm);
+  }
   template <int D, int P, class T>
   int operator()() {
     auto m = view<T>(d);
     hipStream_t st = d->mesh->ctx->stream;
-    const dim3 ge = grid1(m.n_el, etile_eb<D, P, 1>());
-    const T* tL = (const T*)d->trL;
     if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
     const auto prm = devparams<T>(d->lin_prm, d->lin_dt, (const T*)d->dirtab);
-    hipExtLaunchKernelGGL((k_elem<D, P, T, 1, 1>), ge, dim3(etile_nt<D, 1>()), 0, st, ev_start, ev_stop, 0,
-                          (const T*)d->lin_W, (const T*)x, (const T*)nullptr, (T*)y, tL, m, prm);
+    switch (single_call_variant()) {
+      case 0: launch<D, P, T, 0>(st, m, prm); break;
+      case 2: launch<D, P, T, 2>(st, m, prm); break;
+      default: launch<D, P, T, 1>(st, m, prm);
+    }
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }
