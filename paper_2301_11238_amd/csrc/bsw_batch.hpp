@@ -277,7 +277,7 @@ struct BatchEngine {
       case K_PREC: return (int)((I->n_el + kPrecEB - 1) / kPrecEB);       // block-Jacobi applies
       case K_VEC: return I->ntile;
       case K_TRACE: return (int)((NFNFC * I->n_el + 255) / 256);
-      case K_COLS: return cols_tiles_for(BS, (int)I->n_el);  // jac_columns_elem workgroups
+      case K_COLS: return dim == 2 ? (int)I->n_el : cols_tiles_for(BS, (int)I->n_el);  // diagonal-block workgroups
     }
     return 1;
   }
@@ -396,7 +396,11 @@ struct BatchEngine {
     auto f = [&]<int D, int PP, class TT>() -> int {
       BatchSet Sc;
       const int ncol = build(Sc, B, K_COLS);
-      hipLaunchKernelGGL((kb_jac_columns<D, PP, TT>), dim3(ncol), dim3(256), 0, c->stream, d_desc, Sc, (int)B_W);
+      if constexpr (D == 2)
+        hipLaunchKernelGGL((kb_jac_blocks_tri<PP, TT>), dim3(ncol), dim3(JB2<PP>::NT), 0, c->stream, d_desc, Sc,
+                           (int)B_W);
+      else
+        hipLaunchKernelGGL((kb_jac_columns<D, PP, TT>), dim3(ncol), dim3(256), 0, c->stream, d_desc, Sc, (int)B_W);
       HIPCHK(c, hipGetLastError());
       hipLaunchKernelGGL((kb_schur_build<D, PP, TT>), dim3(nt), dim3(256), 0, c->stream, d_desc, S);
       HIPCHK(c, hipGetLastError());

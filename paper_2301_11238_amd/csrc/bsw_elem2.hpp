@@ -430,6 +430,178 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
   }
 }
 
+// Diagonal block dR_e/dW_e of a triangle from pointwise tangents.  The
+// residual's dependence on the element's own coefficient (g, j) enters only
+// through the point states, as phi_j(q) e_g at a volume point and
+// phi_j(p) e_g on the element's side of a face point (the neighbour's side
+// fixed; at a boundary face the exterior state follows the interior one
+// through its own tangent).  The integrands' tangents are linear in that
+// direction, so
+//   B[(f,i),(g,j)] = sum_q C_fi(o_q^g) phi_j(q) + sum_p L_fi(o_p^g) phi_j(p)
+//                    + mass terms,
+// where o_q^g (o_p^g) are the volume (face) integrands' tangents along the
+// unit direction e_g at the point, and C_fi, L_fi the contraction and lift of
+// row (f, i) (the same maps as the element pass's stages 2 and 4).  One
+// workgroup per element: phase A, one lane per (point, direction), 24 x 7
+// lanes at P3, parks the tangents in LDS; phase B, one lane per (row, column
+// field), contracts them with the test functions and writes the row's 10
+// entries of that column field.  Against one lane per column evaluating
+// every point's tangent along that column (70 evaluations of the stress
+// tangent per point at P3), the pointwise work falls by N_p and the
+// contraction is a product with the basis tables.
+template <int P>
+struct JB2 {
+  using S = Shape<2, P>;
+  static constexpr int NFP = S::NFC * S::NFQ;     // face points
+  static constexpr int NPT = S::NQ + NFP;         // points
+  static constexpr int NA = NPT * S::NF;          // phase-A items
+  static constexpr int NBI = S::BS * S::NF;       // phase-B items (row, column field)
+  static constexpr int NT = 256;
+};
+
+template <int P, class T>
+__device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T* __restrict__ trW,
+                                               T* __restrict__ blocks, const MeshView<T>& m, const DevParams<T>& p,
+                                               int e) {
+  using S = Shape<2, P>;
+  using J = JB2<P>;
+  const Tab<2, P, T>& tb = tab<2, P, T>();
+  const int n = m.n_el;
+  const int t = (int)threadIdx.x;
+  __shared__ T sc[S::BS];                      // the element's coefficients
+  __shared__ T sv[S::NQ][S::NF][10];           // volume integrand tangents
+  __shared__ T sf[J::NFP][S::NF][5];           // face integrand tangents
+  __shared__ T snv[S::NFC][2];                 // face normals
+  for (int k = t; k < S::BS; k += J::NT) sc[k] = W[(size_t)k * n + e];
+  if (t < S::NFC * 2) snv[t / 2][t % 2] = m.nrm[(size_t)t * n + e];
+  __syncthreads();
+  Geo<2, T> geo;
+  load_geo<2, T>(m, e, geo);
+  // ---------------- phase A: pointwise tangents along e_g
+  for (int a = t; a < J::NA; a += J::NT) {
+    const int pt = a / S::NF, g = a % S::NF;
+    T X[S::NF], dX[S::NF];
+#pragma unroll
+    for (int f = 0; f < S::NF; ++f) dX[f] = f == g ? T(1) : T(0);
+    if (pt < S::NQ) {
+      const int q = pt;
+#pragma unroll
+      for (int f = 0; f < S::NF; ++f) {
+        T v = T(0);
+#pragma unroll
+        for (int i = 0; i < S::NP; ++i) v += tb.phi[q][i] * sc[f * S::NP + i];
+        X[f] = v;
+      }
+      Pt<2, T> st, ds;
+      unpack<2, T>(X, st);
+      unpack<2, T>(dX, ds);
+      Stress<2, T> sg;
+      stress<2, T>(p, st.E, sg);
+      T sl[2];
+      source_slope<2, P, T>(tb, q, geo, m, p, e, sl);
+      T o[10];
+      e2_vol_tan<T>(p, geo, tb.qw[q] * geo.detJ, st, sg, ds, sl, o);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) sv[q][g][k] = o[k];
+    } else {
+      const int kp = pt - S::NQ, fc = kp / S::NFQ, rr = kp % S::NFQ;
+      const int code = m.nbr[(size_t)fc * n + e];
+#pragma unroll
+      for (int f = 0; f < S::NF; ++f) {
+        T v = T(0);
+#pragma unroll
+        for (int i = 0; i < S::NP; ++i) v += tb.fphi[fc][rr][i] * sc[f * S::NP + i];
+        X[f] = v;
+      }
+      const T nv[2] = {snv[fc][0], snv[fc][1]};
+      Pt<2, T> sm, sp, dsm, dsp;
+      unpack<2, T>(X, sm);
+      unpack<2, T>(dX, dsm);
+      if (code >= 0) {
+        T Xp[S::NF], z[S::NF];
+        load_trace<2, P, T>(trW, n, code >> 2, code & 3, S::NFQ - 1 - rr, Xp);
+#pragma unroll
+        for (int f = 0; f < S::NF; ++f) z[f] = T(0);
+        unpack<2, T>(Xp, sp);
+        unpack<2, T>(z, dsp);
+      } else {
+        exterior<2, T>(p, nv, -1 - code, sm, sp);
+        exterior_tan<2, T>(p, nv, -1 - code, dsm, dsp);
+      }
+      T o[5];
+      e2_face_tan<T>(p, nv, tb.fw[rr] * m.hlen[(size_t)fc * n + e], sm, sp, dsm, dsp, o);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) sf[kp][g][k] = o[k];
+    }
+  }
+  __syncthreads();
+  // ---------------- phase B: rows (f, i) of column field g
+  T* blk = blocks + (size_t)e * S::BS * S::BS;
+  for (int b = t; b < J::NBI; b += J::NT) {
+    const int row = b / S::NF, g = b % S::NF;
+    const int f = row / S::NP, i = row % S::NP;
+    T out[S::NP];
+    if (row_unused<2, T>(m, f, i)) {
+#pragma unroll
+      for (int j = 0; j < S::NP; ++j) out[j] = (g * S::NP + j == row) ? T(1) : T(0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < S::NP; ++j) out[j] = T(0);
+      // volume: C_fi(o_q^g) per point, then times phi_j(q)
+#pragma unroll 1
+      for (int q = 0; q < S::NQ; ++q) {
+        const T* o = sv[q][g];
+        T c;
+        if (f < 3) {
+          c = tb.dphi[q][i][0] * o[2 + f] + tb.dphi[q][i][1] * o[5 + f];
+          if (f > 0) c += tb.phi[q][i] * o[f - 1];
+        } else {
+          const int bb = (f - 3) >> 1, aa = (f - 3) & 1;
+          c = (tb.dphi[q][i][0] * geo.xi[0][aa] + tb.dphi[q][i][1] * geo.xi[1][aa]) * o[8 + bb];
+        }
+#pragma unroll
+        for (int j = 0; j < S::NP; ++j) out[j] += c * tb.phi[q][j];
+      }
+      // faces: L_fi(o_p^g) per point, then times the face basis
+#pragma unroll 1
+      for (int kp = 0; kp < J::NFP; ++kp) {
+        const int fc = kp / S::NFQ, rr = kp % S::NFQ;
+        const T* o = sf[kp][g];
+        T c;
+        if (f < 3) {
+          c = o[f];
+        } else {
+          const int bb = (f - 3) >> 1, aa = (f - 3) & 1;
+          c = o[3 + bb] * snv[fc][aa];
+        }
+        c *= tb.fphi[fc][rr][i];
+#pragma unroll
+        for (int j = 0; j < S::NP; ++j) out[j] += c * tb.fphi[fc][rr][j];
+      }
+      // mass terms: |J| / dt on the depth rows, |J| on the gradient rows
+      if (g == f && (f == 0 || f >= 3)) {
+        const T ms = f == 0 ? geo.detJ * p.inv_dt : geo.detJ;
+#pragma unroll
+        for (int j = 0; j < S::NP; ++j)
+          if (j == i) out[j] += ms;
+      }
+      // columns of unused modes are unit columns
+#pragma unroll
+      for (int j = 0; j < S::NP; ++j)
+        if (row_unused<2, T>(m, g, j)) out[j] = T(0);
+    }
+    T* dst = blk + (size_t)row * S::BS + g * S::NP;
+#pragma unroll
+    for (int j = 0; j < S::NP; ++j) dst[j] = out[j];
+  }
+}
+
+template <int P, class T>
+__global__ void __launch_bounds__(256) k_jac_blocks_tri(const T* __restrict__ W, const T* __restrict__ trW,
+                                                         T* __restrict__ blocks, MeshView<T> m, DevParams<T> p) {
+  jac_blocks_tri<P, T>(W, trW, blocks, m, p, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // Element-pass tile shapes (the autotuner's variants v = 0, 1, 2).  On
 // triangles a workgroup of 4 waves on a tile of 64 elements, compiled for at
 // least 1, 2 or 3 resident waves per SIMD (a register budget of 512, 256 or

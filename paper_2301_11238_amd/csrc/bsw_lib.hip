@@ -585,10 +585,13 @@ struct LinearizeLaunch {
     if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
     hipLaunchKernelGGL((k_trace<D, P, T>), grid1((int64_t)S::NF * S::NFC * m.n_el), dim3(256), 0, c->stream,
                        (const T*)d->lin_W, (T*)d->trL, m.n_el);
-    hipLaunchKernelGGL((k_jac_columns<D, P, T>), dim3(cols_tiles_for(S::BS, m.n_el)), dim3(256), 0, c->stream,
-                       (const T*)d->lin_W,
-                       (const T*)d->trL, (T*)d->blocks_raw, m, devparams<T>(d->lin_prm, d->lin_dt,
-                                                                            (const T*)d->dirtab));
+    const auto prm = devparams<T>(d->lin_prm, d->lin_dt, (const T*)d->dirtab);
+    if constexpr (D == 2)
+      hipLaunchKernelGGL((k_jac_blocks_tri<P, T>), dim3(m.n_el), dim3(JB2<P>::NT), 0, c->stream, (const T*)d->lin_W,
+                         (const T*)d->trL, (T*)d->blocks_raw, m, prm);
+    else
+      hipLaunchKernelGGL((k_jac_columns<D, P, T>), dim3(cols_tiles_for(S::BS, m.n_el)), dim3(256), 0, c->stream,
+                         (const T*)d->lin_W, (const T*)d->trL, (T*)d->blocks_raw, m, prm);
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL((k_schur_build<D, P, T>), dim3((unsigned)((m.n_el + kSchurEPB - 1) / kSchurEPB)), dim3(256), 0,
                        c->stream, (const T*)d->blocks_raw, (float*)d->blocks, m.n_el);
