@@ -341,6 +341,7 @@ def c2_solve(ctx):
         states[name] = W.double().cpu().numpy()
         out[name] = {"ms_per_step": 1e3 * el / n, "newton_per_step": st["newton_total"] / n,
                      "gmres_per_step": st["gmres_total"] / n, "capped_steps": st["capped"],
+                     "meets_accuracy_bar": st["capped"] == 0,
                      "max_mass_drift": st["max_mass_drift"], "dof_steps_per_s": d.state_len() * n / el}
         d.close()
     a, b = states["fp32_mixed"], states["fp64"]
@@ -491,7 +492,10 @@ def request_stream(ctx, seconds, rate, steps, prec, slots, max_waiting=64, drain
     out = {"gmres_max_iters": STREAM_GMRES_MAX, "offered": len(arrivals),
            "offered_large": sum(1 for a in arrivals if a[1] == "large"),
            "submitted": len(sub), "rejected_queue_full": rejected, "completed": done,
-           "completed_with_capped_steps": capped, "cancelled_after_drain": unfinished,
+           "completed_with_capped_steps": capped,
+           "note_capped": "a request with a capped step did not meet the accuracy bar (Newton stopped at its "
+                          "cap of 10 iterations); it is counted as served, not as converged",
+           "cancelled_after_drain": unfinished,
            "achieved_solves_per_s": sum(done.values()) / T, "seconds": T, "peak_resident": info["peak_resident"]}
     for kind in ("c4", "large"):
         out[f"p50_s_{kind}"] = pct(lat[kind], 50)
@@ -532,7 +536,9 @@ def ensemble(ctx, n_inst, steps):
             "triangles_total": int(sum(p.n_el for p in probs)),
             "dofs_total": int(sum(p.n_dof for p in probs)), "seconds": T, "solves_per_s": n_inst / T,
             "peak_resident": info["peak_resident"], "kernel_launches": info["launches"],
-            "per_order": dict(per_order)}
+            "per_order": dict(per_order),
+            "note_capped": "'capped' counts instances with a step that stopped at the Newton cap: those did "
+                           "not meet the accuracy bar"}
 
 
 def main():
