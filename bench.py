@@ -14,14 +14,16 @@ independent sets so every apply reads from HBM (HIP events on the library's
 stream).  The Jacobian-apply rate is reported beside it.
 
 One step (--steps, --warmup) = one pass over the whole hot path on the same
-mesh and state: b_old (a1), the residual (a2-a4), the linearisation (a5:
-traces, diagonal blocks, their Schur-complement factors), one restarted-GMRES cycle of 30
-block-Jacobi-preconditioned matrix-free Jacobian applies (a5, a7), the Newton
-update with its line search and the FP64 reductions (a6): one Newton
-iteration of one backward-Euler time step.  ms_per_step is its time.
+mesh and state: b_old, the residual, the linearisation (traces, diagonal
+blocks, their Schur-complement factors), one restarted-GMRES cycle of 30
+block-Jacobi-preconditioned matrix-free Jacobian applies, the Newton update
+with its line search and the FP64 reductions: one Newton iteration of one
+backward-Euler time step.  ms_per_step is its time.
 
 Other blocks: the same applies in FP32 with their error against FP64; the
-2-D incline configuration (8192 triangles, P2) solved to Newton convergence;
+2-D incline configuration (8192 triangles, P2) solved to Newton convergence,
+and its first two steps against the FP64 oracle's stored result (FP64 and
+FP32-mixed, scored in the CPU-baseline leg);
 the batched FP32 solve server against plain one-at-a-time FP64 solves (solves/s
 and p50/p99 time-to-solution under the same arrivals); the stated request
 stream (Poisson arrivals at 200/s, 2 % 999,698-triangle incline runs,
@@ -349,7 +351,46 @@ def c2_solve(ctx):
     out["fp32_mixed"]["rel_l2_hu_vs_fp64"] = float(np.linalg.norm(a[1:3] - b[1:3]) /
                                                    max(np.linalg.norm(b[1:3]), 1e-300))
     out["workload"] = "2-D incline, 64x64 jittered -> 8192 triangles, P2, reg 1, eps 1e-3, 5 steps after 1"
+    # the first two steps from the initial state with the Krylov solves run to
+    # 1e-13, for the comparison with the stored oracle result (cpu_baseline leg)
+    parity = {}
+    for name, prec in (("fp64", bsw.BSW_FP64), ("fp32_mixed", bsw.BSW_FP32)):
+        d = bsw.Disc(mesh, pb.P, prec)
+        W = d.project_ic(pb.ic)
+        dt = d.cfl_dt(cp, W, pb.cfl)
+        for _ in range(2):
+            d.solve(cp, bsw.Options(t_end=10 * dt, dt=dt, max_steps=1, gmres_rtol=1e-13, forcing_max=1e-13,
+                                    gmres_m=60, gmres_max_iters=5000), W)
+        parity[name] = W.double().cpu().numpy()
+        d.close()
     mesh.close()
+    return out, parity
+
+
+def oracle_parity(states):
+    """The incline's first two steps (reg 1, eps 1e-3; FP64 and FP32-mixed)
+    against the oracle's result stored in tests/golden/c2_first_steps.json:
+    relative L2 of h and h u at the volume points of the stored sample of 64
+    elements, the points evaluated by the oracle."""
+    import json
+    import numpy as np
+    import oracle
+    import workloads as wl
+    with open(os.path.join(ROOT, "tests", "golden", "c2_first_steps.json")) as f:
+        g = next(r for r in json.load(f)["runs"] if r["reg"] == wl.REG1 and r["eps"] == 1e-3)
+    pb = wl.config2(wl.REG1, 1e-3)
+    orc = oracle.Oracle(2, pb.P, pb.xy, pb.el2vert)
+    idx = np.asarray(g["elements"])
+    hs, hus = np.asarray(g["h"]), np.asarray(g["hu"])
+    out = {"workload": "2-D incline, 8192 triangles, P2, reg 1, eps 1e-3: the first two steps",
+           "reference": "FP64 oracle (stored), Krylov solves to 1e-13 on both sides"}
+    for name, bar in (("fp64", 1e-10), ("fp32_mixed", 1e-5)):
+        vals = orc.eval_points(states[name])
+        h = vals[..., 0]
+        hu = vals[..., :1] * vals[..., 1:3]
+        eh = float(np.linalg.norm(h[idx] - hs) / np.linalg.norm(hs))
+        eq = float(np.linalg.norm(hu[idx] - hus) / np.linalg.norm(hus))
+        out[name] = {"rel_l2_h": eh, "rel_l2_hu": eq, "bar": bar, "within_bar": eh <= bar and eq <= bar}
     return out
 
 
@@ -661,8 +702,9 @@ def main():
     disc.close()
     mesh.close()
     torch.cuda.synchronize()
+    parity_states = None
     if not args.no_c2:
-        out["c2_solve"] = c2_solve(ctx)
+        out["c2_solve"], parity_states = c2_solve(ctx)
         log("incline solve done")
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests, args.serve_steps)
@@ -678,6 +720,8 @@ def main():
         log("ensemble done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
+        if parity_states is not None:
+            out["oracle_parity"] = oracle_parity(parity_states)
         log("CPU baseline done")
     print(json.dumps(out))
 
