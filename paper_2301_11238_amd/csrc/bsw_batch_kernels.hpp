@@ -90,6 +90,31 @@ __device__ __forceinline__ double bred(double v, int op) {
   return r;
 }
 
+// Sum (op 0), maximum (1) or minimum (2) of the partials p[0 .. nt) by a
+// 256-lane workgroup, in a fixed order: lane l keeps eight accumulators,
+// accumulator u taking p[2048 k + 256 u + l] for k = 0, 1, ...; the eight are
+// combined in order u = 0..7, then over the workgroup (bred).  The eight loads
+// of a round are independent, so a round costs one memory latency, not eight.
+// Every fold of one set of partials goes through here, so the result does
+// not depend on which kernel folded it.
+__device__ __forceinline__ double fold_partials(const double* __restrict__ p, int nt, int op) {
+  const double init = op == 0 ? 0.0 : (op == 1 ? -INFINITY : INFINITY);
+  double a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = init;
+  for (int base = (int)threadIdx.x; base < nt; base += 2048) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = base + 256 * u < nt ? p[base + 256 * u] : init;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = op == 0 ? a[u] + v[u] : (op == 1 ? fmax(a[u], v[u]) : fmin(a[u], v[u]));
+  }
+  double acc = a[0];
+#pragma unroll
+  for (int u = 1; u < 8; ++u) acc = op == 0 ? acc + a[u] : (op == 1 ? fmax(acc, a[u]) : fmin(acc, a[u]));
+  return bred(acc, op);
+}
+
 // ------------------------------------------------------------------ element stages
 template <int D, int P, class T>
 __global__ void __launch_bounds__(256) kb_step_begin(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW,
@@ -174,7 +199,7 @@ __global__ void __launch_bounds__(256) kb_prec_apply(const InstDesc<T>* __restri
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int j = A.jv[ai];
-  schur_apply_tile<D, P, T>(I.blk, bslot(I, sX, j), bslot(I, sY, j), I.m.n_el,
+  schur_apply_tile<D, P, T>(I.blk, bslot(I, sX, j), bslot(I, sY, j), I.m, I.p.bc,
                             ((int)blockIdx.x - A.tile0[ai]) * kPrecEB, [] { return 1.0; });
 }
 
@@ -545,9 +570,7 @@ __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restr
   const bool first = b == A.tile0[ai];
   auto sigma = [&]() -> double {
     if (!fold) return sc[(int64_t)slot * kScStride + kScS + j];
-    double acc = 0.0;
-    for (int t = threadIdx.x; t < I.ntile; t += 256) acc += I.part[t];
-    const double nrm = sqrt(bred(acc, 0));
+    const double nrm = sqrt(fold_partials(I.part, I.ntile, 0));
     const double sgm = nrm > 0.0 ? 1.0 / nrm : 0.0;
     if (first && threadIdx.x == 0) {
       double* sd = sc + (int64_t)slot * kScStride;
@@ -559,7 +582,7 @@ __global__ void __launch_bounds__(256) kb_prec_krylov(const InstDesc<T>* __restr
     }
     return sgm;
   };
-  schur_apply_tile<D, P, T>(I.blk, bslot(I, sV0, 0) + (int64_t)j * I.ld, bslot(I, sZ, 0), I.m.n_el,
+  schur_apply_tile<D, P, T>(I.blk, bslot(I, sV0, 0) + (int64_t)j * I.ld, bslot(I, sZ, 0), I.m, I.p.bc,
                             (b - A.tile0[ai]) * kPrecEB, sigma);
 }
 
@@ -608,12 +631,7 @@ __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restri
   const int op = r < 16 ? (int)((ops >> (2 * r)) & 3u) : 0;
   const int nt = etile ? I.ntile_e : I.ntile;
   const bool skipped = gate >= 0 && !gs_refine(sc + (int64_t)slot * kScStride + gate, A.jv[ai] + 1);
-  double acc = op == 0 ? 0.0 : (op == 1 ? -INFINITY : INFINITY);
-  for (int t = threadIdx.x; t < (skipped ? 0 : nt); t += 256) {
-    const double v = I.part[(int64_t)r * nt + t];
-    acc = op == 0 ? acc + v : (op == 1 ? fmax(acc, v) : fmin(acc, v));
-  }
-  double x = bred(acc, op);
+  double x = fold_partials(I.part + (int64_t)r * nt, skipped ? 0 : nt, op);
   if (threadIdx.x == 0) {
     double* s = sc + (int64_t)slot * kScStride;
     double* sh = sch + (int64_t)slot * kScStride;

@@ -733,15 +733,19 @@ __global__ void __launch_bounds__(256) k_jac_columns(const T* __restrict__ W, co
 // So the Schur complement S = A_VV - A_VE D^{-1} A_EV differs from A_VV only
 // in its U x U part, and the block solve z = A^{-1} x is
 //   z_V = S^{-1} (x_V - A_VE D^{-1} x_E),   z_E = D^{-1} x_E - D^{-1} A_EU z_U.
-// Per element the factors S^{-1} (NV x NV), G = A_UE (NU x NE),
-// H = D^{-1} A_EU (NE x NU) and d = D^{-1} (NE) are stored, in FP32 and
-// element fastest (number k of element e at F[k * n + e]): 2540 numbers at P3
-// on triangles against 4900 for the whole inverse, from a 30-row inversion
-// instead of a 70-row one.  FP32 for both state precisions: the
-// preconditioner only steers GMRES (the Krylov residual uses the exact
-// Jacobian) and its apply reads half the bytes.  A_EE's off-diagonal entries
-// are quadrature rounding of zero (about 1e-13 of the diagonal) and are not
-// read.
+// Per element the factors S^{-1} (NV x NV) and G = A_UE (NU x NE) are stored,
+// in FP32 and element fastest (number k of element e at F[k * n + e]).  On
+// triangles D^{-1} A_EU and D^{-1} are not stored: the stress equations'
+// dependence on the velocity is linear with state-independent coefficients
+// (the weak gradient: the volume term and the central face trace), so
+// D^{-1} A_EU z_U is evaluated in the apply from the element's geometry, its
+// boundary codes and the reference tables, and D = |J| I; 1700 numbers per
+// element at P3 against 4900 for the whole inverse, from a 30-row inversion
+// instead of a 70-row one.  In 1-D H = D^{-1} A_EU (NE x NU) and d = D^{-1}
+// (NE) are stored too.  FP32 for both state precisions: the preconditioner
+// only steers GMRES (the Krylov residual uses the exact Jacobian) and its
+// apply reads half the bytes.  A_EE's off-diagonal entries are quadrature
+// rounding of zero (about 1e-13 of the diagonal) and are not read.
 template <int D, int P>
 struct Schur {
   static constexpr int NP = Shape<D, P>::NP;
@@ -749,16 +753,18 @@ struct Schur {
   static constexpr int NV = (1 + D) * NP;  // depth and velocity rows
   static constexpr int NU = D * NP;        // velocity rows, NP .. NV - 1
   static constexpr int NE = D * D * NP;    // stress rows, NV .. BS - 1
+  static constexpr bool GEO = D == 2;     // D^{-1} A_EU from the geometry
   static constexpr int OS = 0;             // S^{-1}, row-major
   static constexpr int OG = NV * NV;       // G = A_UE, row-major
-  static constexpr int OH = OG + NU * NE;  // H = D^{-1} A_EU, row-major
-  static constexpr int OD = OH + NE * NU;  // d = D^{-1}
-  static constexpr int NB = OD + NE;       // numbers per element
+  static constexpr int OH = OG + NU * NE;  // H = D^{-1} A_EU, row-major (1-D)
+  static constexpr int OD = OH + NE * NU;  // d = D^{-1} (1-D)
+  static constexpr int NB = GEO ? OH : OD + NE;  // numbers per element
   static_assert(NV <= 64, "the Schur complement rows must fit one wave");
 };
 // numbers per element of the stored factors (host side)
 constexpr int schur_numbers(int dim, int np) {
-  return ((1 + dim) * np) * ((1 + dim) * np) + 2 * (dim * np) * (dim * dim * np) + dim * dim * np;
+  return ((1 + dim) * np) * ((1 + dim) * np) + (dim == 2 ? 1 : 2) * (dim * np) * (dim * dim * np) +
+         (dim == 2 ? 0 : dim * dim * np);
 }
 
 // the device library's wave reduction of 64-bit keys (its 32-bit siblings are
@@ -840,13 +846,15 @@ __device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float*
   if (lane < Z::NE) {
     const T di = T(1) / dd;
     sD[w][lane] = di;
-    if (live) out[(size_t)(Z::OD + lane) * n] = (float)di;
+    if (!Z::GEO && live) out[(size_t)(Z::OD + lane) * n] = (float)di;
   }
   __syncthreads();
+  if constexpr (!Z::GEO) {
 #pragma unroll
-  for (int j = 0; j < JH; ++j) {
-    const int i = lane + 64 * j;
-    if (live && i < NH) out[(size_t)(Z::OH + i) * n] = (float)(a[j] * sD[w][i / Z::NU]);
+    for (int j = 0; j < JH; ++j) {
+      const int i = lane + 64 * j;
+      if (live && i < NH) out[(size_t)(Z::OH + i) * n] = (float)(a[j] * sD[w][i / Z::NU]);
+    }
   }
   float* gout = out + (size_t)(Z::OG + (vel ? lane - Z::NP : 0) * Z::NE) * n;
 #pragma unroll 1
@@ -908,30 +916,100 @@ __global__ void __launch_bounds__(256) k_schur_build(const T* __restrict__ A, fl
   schur_build_elem<D, P, T>(A, F, n, e, e < n);
 }
 
+// On triangles, row (b, a, k) of D^{-1} A_EU z_U (stress row E_ab, mode k;
+// z_U the velocity coefficients), from the element's residual of the weak
+// gradient: the volume term sum_q w_q |J| (grad phi_k . xi_.a) u_b and the
+// face term -sum_r w_r (|face| / 2) phi_k (u_b^- + u_b^+) / 2 n_a, whose
+// own-side derivative carries I + du^+/du^- with du^+/du^- = 0 across interior faces
+// and at Dirichlet faces, I at Neumann faces and I - 2 n n^T at walls (the
+// exterior states of the boundary kinds); divided by D = |J|.  zq: z_b at the
+// volume points; zf[fc][rr][c]: z_c at the face points (unused velocity
+// modes masked out: their columns of A_EU are unit columns of the block).
+template <int P, class T>
+__device__ __forceinline__ void schur_geo_rows(const Tab<2, P, T>& tb, const MeshView<T>& m, int bc, unsigned e,
+                                               int b, int a, const double (&zq)[Shape<2, P>::NQ],
+                                               const double (&zf)[3][Shape<2, P>::NFQ][2], double (&hz)[Shape<2, P>::NP]) {
+  using S = Shape<2, P>;
+  const int n = m.n_el;
+  const double inv_det = 1.0 / (double)rowld(m.detJ, 0, n, e);
+  const double xa0 = (double)rowld(m.dxi, 0 * 2 + a, n, e), xa1 = (double)rowld(m.dxi, 1 * 2 + a, n, e);
+  // the face coefficients c_fc[rr] = sum_c beta_fc[b][c] zf[fc][rr][c], with
+  // the factor -(|face| / 2) n_a / (2 |J|) (hlen holds |face| / 2)
+  double cf[3][S::NFQ];
+#pragma unroll
+  for (int fc = 0; fc < 3; ++fc) {
+    const int code = rowld(m.nbr, fc, n, e);
+    const double n0 = (double)rowld(m.nrm, fc * 2 + 0, n, e), n1 = (double)rowld(m.nrm, fc * 2 + 1, n, e);
+    const double hl = (double)rowld(m.hlen, fc, n, e);
+    int kind = 0;  // 0: the exterior side is fixed (interior face or Dirichlet)
+    if (code < 0) {
+      const int cb = -1 - code;
+      kind = (cb & 3) ? (cb & 3) : bc;
+      if (kind == 3) kind = 0;
+    }
+    const double nb = b == 0 ? n0 : n1, na = a == 0 ? n0 : n1;
+    // beta row b
+    double b0 = b == 0 ? 1.0 : 0.0, b1 = b == 1 ? 1.0 : 0.0;
+    if (kind == 2) { b0 *= 2.0; b1 *= 2.0; }
+    if (kind == 1) { b0 = 2.0 * (b0 - nb * n0); b1 = 2.0 * (b1 - nb * n1); }
+    const double sc = -0.5 * hl * na * inv_det;
+#pragma unroll
+    for (int rr = 0; rr < S::NFQ; ++rr) cf[fc][rr] = sc * (double)tb.fw[rr] * (b0 * zf[fc][rr][0] + b1 * zf[fc][rr][1]);
+  }
+#pragma unroll
+  for (int k = 0; k < S::NP; ++k) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < S::NQ; ++q)
+      v += (double)tb.qw[q] * ((double)tb.dphi[q][k][0] * xa0 + (double)tb.dphi[q][k][1] * xa1) * zq[q];
+#pragma unroll
+    for (int fc = 0; fc < 3; ++fc)
+#pragma unroll
+      for (int rr = 0; rr < S::NFQ; ++rr) v += (double)tb.fphi[fc][rr][k] * cf[fc][rr];
+    hz[k] = v;
+  }
+}
+
 // Block solve of 64 consecutive elements by a workgroup of four waves, one
 // lane per element.  x is staged in LDS (the stress rows already scaled by
 // D^{-1}); then r_U = x_U - G t_E replaces x_U, z_V = S^{-1} r_V is written
-// and z_U replaces r_U, and z_E = t_E - H z_U is written.  The waves take the
-// rows of each phase in turn.  Every factor row is a coalesced read of 64
-// consecutive FP32 numbers.  scale() (called once by every thread, after the
-// first phase) gives the factor applied to the written z.
+// and z_U replaces r_U, and z_E = t_E - D^{-1} A_EU z_U is written (on
+// triangles each wave takes one stress field and forms D^{-1} A_EU z_U from
+// the geometry; in 1-D from the stored H).  The waves take the rows of each
+// phase in turn.  Every factor row is a coalesced read of 64 consecutive FP32
+// numbers.  scale() (called once by every thread, after the first phase)
+// gives the factor applied to the written z.  m and bc (the boundary kind of
+// faces coded 0) serve the geometric rows.
 constexpr int kPrecEB = 64;
 template <int D, int P, class T, class Scale>
 __device__ __forceinline__ void schur_apply_tile(const float* __restrict__ F, const T* __restrict__ x,
-                                                 T* __restrict__ y, int n, int e0, Scale scale) {
+                                                 T* __restrict__ y, const MeshView<T>& m, int bc, int e0,
+                                                 Scale scale) {
   using Z = Schur<D, P>;
+  using S = Shape<D, P>;
   constexpr int NW = 4;
+  const int n = m.n_el;
   __shared__ double xs[Z::BS][kPrecEB];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const unsigned e = (unsigned)(e0 + lane);
   const bool live = (int)e < n;
   auto ld = [&](int k) -> double { return (double)rowld(F, k, n, e); };
+  double inv_det = 1.0;
+  if constexpr (Z::GEO) {
+    if (live) inv_det = 1.0 / (double)rowld(m.detJ, 0, n, e);
+  }
   for (int r = w; r < Z::BS; r += NW) {
     double v = 0.0;
     if (live) {
       v = (double)rowld(x, r, n, e);
-      if (r >= Z::NV) v *= ld(Z::OD + r - Z::NV);
+      if (r >= Z::NV) {
+        if constexpr (Z::GEO) {
+          if (!row_unused<D, T>(m, r / Z::NP, r % Z::NP)) v *= inv_det;
+        } else {
+          v *= ld(Z::OD + r - Z::NV);
+        }
+      }
     }
     xs[r][lane] = v;
   }
@@ -967,18 +1045,55 @@ __device__ __forceinline__ void schur_apply_tile(const float* __restrict__ F, co
   }
   __syncthreads();
   if (!live) return;
-  for (int k = w; k < Z::NE; k += NW) {
-    double s = xs[Z::NV + k][lane];
+  if constexpr (Z::GEO) {
+    static_assert(D * D == NW, "one stress field per wave");
+    const Tab<2, P, T>& tb = tab<2, P, T>();
+    const int fe = 3 + w, b = w >> 1, a = w & 1;
+    double zq[S::NQ], zf[3][S::NFQ][2];
 #pragma unroll
-    for (int c = 0; c < Z::NU; ++c) s -= ld(Z::OH + k * Z::NU + c) * xs[Z::NP + c][lane];
-    rowref(y, Z::NV + k, n, e) = (T)(sg * s);
+    for (int q = 0; q < S::NQ; ++q) zq[q] = 0.0;
+#pragma unroll
+    for (int fc = 0; fc < 3; ++fc)
+#pragma unroll
+      for (int rr = 0; rr < S::NFQ; ++rr) zf[fc][rr][0] = zf[fc][rr][1] = 0.0;
+#pragma unroll
+    for (int j = 0; j < S::NP; ++j) {
+      if (row_unused<D, T>(m, 1, j)) continue;  // (the two velocity fields share their order)
+      const double z0 = xs[S::NP + j][lane], z1 = xs[2 * S::NP + j][lane];
+      const double zb = b == 0 ? z0 : z1;
+#pragma unroll
+      for (int q = 0; q < S::NQ; ++q) zq[q] += (double)tb.phi[q][j] * zb;
+#pragma unroll
+      for (int fc = 0; fc < 3; ++fc)
+#pragma unroll
+        for (int rr = 0; rr < S::NFQ; ++rr) {
+          zf[fc][rr][0] += (double)tb.fphi[fc][rr][j] * z0;
+          zf[fc][rr][1] += (double)tb.fphi[fc][rr][j] * z1;
+        }
+    }
+    double hz[S::NP];
+    schur_geo_rows<P, T>(tb, m, bc, e, b, a, zq, zf, hz);
+#pragma unroll
+    for (int k = 0; k < S::NP; ++k) {
+      const int row = fe * S::NP + k;
+      double s = xs[row][lane];
+      if (!row_unused<D, T>(m, fe, k)) s -= hz[k];
+      rowref(y, row, n, e) = (T)(sg * s);
+    }
+  } else {
+    for (int k = w; k < Z::NE; k += NW) {
+      double s = xs[Z::NV + k][lane];
+#pragma unroll
+      for (int c = 0; c < Z::NU; ++c) s -= ld(Z::OH + k * Z::NU + c) * xs[Z::NP + c][lane];
+      rowref(y, Z::NV + k, n, e) = (T)(sg * s);
+    }
   }
 }
 
 template <int D, int P, class T>
 __global__ void __launch_bounds__(256) k_schur_apply(const float* __restrict__ F, const T* __restrict__ x,
-                                                      T* __restrict__ y, int n) {
-  schur_apply_tile<D, P, T>(F, x, y, n, (int)blockIdx.x * kPrecEB, [] { return 1.0; });
+                                                      T* __restrict__ y, MeshView<T> m, int bc) {
+  schur_apply_tile<D, P, T>(F, x, y, m, bc, (int)blockIdx.x * kPrecEB, [] { return 1.0; });
 }
 
 // per-element contributions to the mass, the active (yielded) area, the

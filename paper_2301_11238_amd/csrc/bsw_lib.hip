@@ -606,7 +606,7 @@ struct PrecLaunch {
   int operator()() {
     auto m = view<T>(d);
     hipLaunchKernelGGL((k_schur_apply<D, P, T>), dim3((unsigned)((m.n_el + kPrecEB - 1) / kPrecEB)), dim3(256), 0,
-                       d->mesh->ctx->stream, (const float*)d->blocks, (const T*)x, (T*)y, m.n_el);
+                       d->mesh->ctx->stream, (const float*)d->blocks, (const T*)x, (T*)y, m, d->lin_prm.bc);
     HIPCHK(d->mesh->ctx, hipGetLastError());
     return BSW_OK;
   }

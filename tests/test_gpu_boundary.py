@@ -10,7 +10,7 @@ import pytest
 
 import workloads as wl
 from _gpu_util import Pair, have_gpu, mesh_for, relerr
-from test_gpu_parity import rel_l2_h_hu
+from test_gpu_parity import assert_preconditioner_matches, rel_l2_h_hu
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
 
@@ -61,6 +61,9 @@ def test_operator_and_jacobian_with_face_codes(ctx, dim, P, n, default_bc):
     Bg = pr.host(pr.disc.jacobian_blocks())
     Bo = pr.orc.jac_blocks(p, W, dt, bc=default_bc, dirichlet=st[0])
     assert np.abs(Bg - Bo).max() <= 1e-12 * np.abs(Bo).max()
+    # the block solve with these faces (on triangles the stress rows of the
+    # block solve are formed from the faces' kinds)
+    assert_preconditioner_matches(pr, dim, x, Bo)
     # the codes changed the result, and resetting them restores the default
     pr.mesh.set_boundary(None)
     R0 = pr.host(pr.disc.operator_apply(cp, dt, pr.dev(W), pr.dev(bo[: 1 + dim])))

@@ -9,7 +9,7 @@ import pytest
 
 import workloads as wl
 from _gpu_util import Pair, have_gpu, mesh_for, relerr
-from test_gpu_parity import rel_l2_h_hu
+from test_gpu_parity import assert_preconditioner_matches, rel_l2_h_hu
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
 
@@ -71,6 +71,7 @@ def test_operator_jacobian_and_blocks_with_mixed_orders(ctx, dim, P, n, orders, 
     Bg = pr.host(pr.disc.jacobian_blocks())
     Bo = pr.orc.jac_blocks(p, W, dt)
     assert np.abs(Bg - Bo).max() <= 1e-12 * np.abs(Bo).max()
+    assert_preconditioner_matches(pr, dim, x, Bo)
 
 
 def test_orders_are_checked_and_reset_the_linearisation(ctx):

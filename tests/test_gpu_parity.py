@@ -89,31 +89,16 @@ def test_operator_other_boundaries(ctx, dim, P, n, bc):
     assert relerr(yg, yo) <= 1e-11
 
 
-@pytest.mark.parametrize("dim,P,n", OP_CASES)
-@pytest.mark.parametrize("reg", [1, 3])
-def test_jacobian_apply_blocks_and_preconditioner(ctx, dim, P, n, reg):
-    from paper_2301_11238_amd import bsw
-    pr = make_pair(ctx, dim, P, n)
-    p = prm_for(reg)
-    W = wl.random_state(dim, P, pr.disc.n_el, 300 + reg)
-    x = wl.random_vector(dim, P, pr.disc.n_el, 301)
-    dt = 0.021
-    cp = bsw.make_params(p)
-    Wd = pr.dev(W)
-    pr.disc.jacobian_linearize(cp, dt, Wd)
-    yg = pr.host(pr.disc.jacobian_apply(pr.dev(x)))
-    yo = pr.orc.jac_apply(p, W, x, dt)
-    assert relerr(yg, yo) <= 1e-11
-    Bg = pr.host(pr.disc.jacobian_blocks())
-    Bo = pr.orc.jac_blocks(p, W, dt)
-    assert np.abs(Bg - Bo).max() <= 1e-12 * np.abs(Bo).max()
-    # preconditioner: the exact block solve y_e = B_e^{-1} x_e, taken through
-    # the Schur complement S = A_VV - A_VE D^{-1} A_EV of the stress block
-    # D = A_EE (diagonal), with the factors S^{-1}, G = A_UE, H = D^{-1} A_EU
-    # and d = D^{-1} stored in FP32.  First-order bound of the rounding of
-    # those factors (u = 2^-24) through
-    #   t = d x_E, r_U = x_U - G t, z_V = S^{-1} r_V, z_E = t - H z_U,
-    # doubled, plus the FP64 inversion error:
+def assert_preconditioner_matches(pr, dim, x, Bo):
+    """precond_apply after a linearise against the exact block solve
+    y_e = B_e^{-1} x_e of the oracle's blocks B.  The library applies it
+    through the Schur complement S = A_VV - A_VE D^{-1} A_EV of the stress
+    block D = A_EE (diagonal), with S^{-1} and G = A_UE stored in FP32 (in 1-D
+    also H = D^{-1} A_EU and d = D^{-1}; on triangles those two come from the
+    geometry in FP64).  First-order bound of the rounding of those factors
+    (u = 2^-24) through
+      t = d x_E, r_U = x_U - G t, z_V = S^{-1} r_V, z_E = t - H z_U,
+    doubled, plus the FP64 inversion error."""
     yp = pr.host(pr.disc.precond_apply(pr.dev(x)))
     nf, np_, ne = pr.shape
     xe = np.transpose(x, (2, 0, 1)).reshape(ne, nf * np_)
@@ -139,6 +124,27 @@ def test_jacobian_apply_blocks_and_preconditioner(ctx, dim, P, n, reg):
     assert np.all(np.abs(ye - ex) <= bound)
     # and not much looser than that: the rounding is visible but small
     assert np.abs(ye - ex).max() <= 1e-5 * np.abs(ex).max()
+
+
+@pytest.mark.parametrize("dim,P,n", OP_CASES)
+@pytest.mark.parametrize("reg", [1, 3])
+def test_jacobian_apply_blocks_and_preconditioner(ctx, dim, P, n, reg):
+    from paper_2301_11238_amd import bsw
+    pr = make_pair(ctx, dim, P, n)
+    p = prm_for(reg)
+    W = wl.random_state(dim, P, pr.disc.n_el, 300 + reg)
+    x = wl.random_vector(dim, P, pr.disc.n_el, 301)
+    dt = 0.021
+    cp = bsw.make_params(p)
+    Wd = pr.dev(W)
+    pr.disc.jacobian_linearize(cp, dt, Wd)
+    yg = pr.host(pr.disc.jacobian_apply(pr.dev(x)))
+    yo = pr.orc.jac_apply(p, W, x, dt)
+    assert relerr(yg, yo) <= 1e-11
+    Bg = pr.host(pr.disc.jacobian_blocks())
+    Bo = pr.orc.jac_blocks(p, W, dt)
+    assert np.abs(Bg - Bo).max() <= 1e-12 * np.abs(Bo).max()
+    assert_preconditioner_matches(pr, dim, x, Bo)
 
 
 def test_stage_update_and_reductions(ctx):
