@@ -799,11 +799,12 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // The factors of element e from its diagonal block A (row-major, [e][row][col])
 // by one wave of a four-wave workgroup (every wave reaches the barrier; live
 // is false for a wave past the last element, whose loads then read element
-// 0's block and whose results are dropped).  D^{-1} goes to the wave's slice
-// of LDS; D^{-1} A_EU is formed and stored by all lanes.  Lane t < NV holds
-// row t of S in registers: the row of A_VV, minus (velocity rows) the
-// products of its A_UE entries, scaled by D^{-1}, with the rows of A_EU, which
-// are wave-uniform and read as scalars.  The loads of each phase go out
+// 0's block and whose results are dropped).  D^{-1}, A_EU and the velocity
+// lanes' A_UE entries go to the wave's slice of LDS (in 1-D D^{-1} A_EU and
+// D^{-1} are also stored as factors).  Lane t < NV holds row t of S in
+// registers: the row of A_VV, minus (velocity rows) the products of its A_UE
+// entries, scaled by D^{-1}, with the rows of A_EU, read back from LDS as
+// broadcasts one stress row at a time.  The loads of each phase go out
 // together, before their first use.  S is inverted by Gauss-Jordan
 // elimination with partial pivoting on [S | I], in place and without row
 // swaps: at step k the lane whose row has the largest |entry| in the current
@@ -825,6 +826,8 @@ __device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float*
   constexpr int JH = (NH + 63) / 64;  // entries of D^{-1} A_EU per lane
   constexpr int KC = Z::NE % 20 == 0 ? 20 : (Z::NE % 8 == 0 ? 8 : Z::NE);  // A_UE entries per batch
   __shared__ T sD[kSchurEPB][Z::NE];
+  __shared__ T sA[kSchurEPB][Z::NE][Z::NU];  // A_EU
+  __shared__ T sG[kSchurEPB][Z::NE][Z::NU];  // A_UE, transposed (velocity lane fastest)
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const T* blk = A + (size_t)(live ? e : 0) * Z::BS * Z::BS;
@@ -856,7 +859,14 @@ __device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float*
       if (live && i < NH) out[(size_t)(Z::OH + i) * n] = (float)(a[j] * sD[w][i / Z::NU]);
     }
   }
+  // A_EU (raw) and the velocity lanes' A_UE entries to the wave's LDS slice;
+  // the A_UE entries also go out as the factor G
   float* gout = out + (size_t)(Z::OG + (vel ? lane - Z::NP : 0) * Z::NE) * n;
+#pragma unroll
+  for (int j = 0; j < JH; ++j) {
+    const int i = lane + 64 * j;
+    if (i < NH) sA[w][i / Z::NU][i % Z::NU] = a[j];
+  }
 #pragma unroll 1
   for (int k0 = 0; k0 < Z::NE; k0 += KC) {
     T g[KC];
@@ -864,18 +874,20 @@ __device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float*
     for (int kk = 0; kk < KC; ++kk) g[kk] = row[Z::NV + k0 + kk];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
-      const int k = k0 + kk;
-      if (vel) gout[(size_t)k * n] = (float)g[kk];
-      const T f = vel ? g[kk] * sD[w][k] : T(0);
-      // stress row k: wave-uniform, read through the constant address space
-      // (the block is not written by this kernel), which makes them scalar
-      // loads also where the compiler cannot prove that the factor stores do
-      // not alias the block
-      const __attribute__((address_space(4))) T* ek =
-          (const __attribute__((address_space(4))) T*)(blk + (size_t)(Z::NV + k) * Z::BS + Z::NP);
-#pragma unroll
-      for (int c = 0; c < Z::NU; ++c) r[Z::NP + c] -= f * ek[c];
+      if (vel) {
+        gout[(size_t)(k0 + kk) * n] = (float)g[kk];
+        sG[w][k0 + kk][lane - Z::NP] = g[kk];
+      }
     }
+  }
+  __syncthreads();
+  // S_UU -= A_UE D^{-1} A_EU, one stress row k at a time: the lane's A_UE
+  // entry and row k of A_EU (a broadcast) from LDS
+#pragma unroll 2
+  for (int k = 0; k < Z::NE; ++k) {
+    const T f = vel ? sG[w][k][lane - Z::NP] * sD[w][k] : T(0);
+#pragma unroll
+    for (int c = 0; c < Z::NU; ++c) r[Z::NP + c] -= f * sA[w][k][c];
   }
   if (!live) return;
   bool used = !own;
