@@ -472,8 +472,20 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
   __shared__ T sv[S::NQ][S::NF][10];           // volume integrand tangents
   __shared__ T sf[J::NFP][S::NF][5];           // face integrand tangents
   __shared__ T snv[S::NFC][2];                 // face normals
+  // the reference tables the lanes read at lane-dependent indices
+  __shared__ T sphi[S::NQ][S::NP], sdphi[S::NQ][S::NP][2], sfphi[S::NFC][S::NFQ][S::NP];
   for (int k = t; k < S::BS; k += J::NT) sc[k] = W[(size_t)k * n + e];
   if (t < S::NFC * 2) snv[t / 2][t % 2] = m.nrm[(size_t)t * n + e];
+  for (int k = t; k < S::NQ * S::NP; k += J::NT) {
+    const int q = k / S::NP, i = k % S::NP;
+    sphi[q][i] = tb.phi[q][i];
+    sdphi[q][i][0] = tb.dphi[q][i][0];
+    sdphi[q][i][1] = tb.dphi[q][i][1];
+  }
+  for (int k = t; k < S::NFC * S::NFQ * S::NP; k += J::NT) {
+    const int fc = k / (S::NFQ * S::NP), rr = (k / S::NP) % S::NFQ, i = k % S::NP;
+    sfphi[fc][rr][i] = tb.fphi[fc][rr][i];
+  }
   __syncthreads();
   Geo<2, T> geo;
   load_geo<2, T>(m, e, geo);
@@ -489,7 +501,7 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
       for (int f = 0; f < S::NF; ++f) {
         T v = T(0);
 #pragma unroll
-        for (int i = 0; i < S::NP; ++i) v += tb.phi[q][i] * sc[f * S::NP + i];
+        for (int i = 0; i < S::NP; ++i) v += sphi[q][i] * sc[f * S::NP + i];
         X[f] = v;
       }
       Pt<2, T> st, ds;
@@ -510,7 +522,7 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
       for (int f = 0; f < S::NF; ++f) {
         T v = T(0);
 #pragma unroll
-        for (int i = 0; i < S::NP; ++i) v += tb.fphi[fc][rr][i] * sc[f * S::NP + i];
+        for (int i = 0; i < S::NP; ++i) v += sfphi[fc][rr][i] * sc[f * S::NP + i];
         X[f] = v;
       }
       const T nv[2] = {snv[fc][0], snv[fc][1]};
@@ -553,11 +565,11 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
         const T* o = sv[q][g];
         T c;
         if (f < 3) {
-          c = tb.dphi[q][i][0] * o[2 + f] + tb.dphi[q][i][1] * o[5 + f];
-          if (f > 0) c += tb.phi[q][i] * o[f - 1];
+          c = sdphi[q][i][0] * o[2 + f] + sdphi[q][i][1] * o[5 + f];
+          if (f > 0) c += sphi[q][i] * o[f - 1];
         } else {
           const int bb = (f - 3) >> 1, aa = (f - 3) & 1;
-          c = (tb.dphi[q][i][0] * geo.xi[0][aa] + tb.dphi[q][i][1] * geo.xi[1][aa]) * o[8 + bb];
+          c = (sdphi[q][i][0] * geo.xi[0][aa] + sdphi[q][i][1] * geo.xi[1][aa]) * o[8 + bb];
         }
 #pragma unroll
         for (int j = 0; j < S::NP; ++j) out[j] += c * tb.phi[q][j];
@@ -574,7 +586,7 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
           const int bb = (f - 3) >> 1, aa = (f - 3) & 1;
           c = o[3 + bb] * snv[fc][aa];
         }
-        c *= tb.fphi[fc][rr][i];
+        c *= sfphi[fc][rr][i];
 #pragma unroll
         for (int j = 0; j < S::NP; ++j) out[j] += c * tb.fphi[fc][rr][j];
       }
