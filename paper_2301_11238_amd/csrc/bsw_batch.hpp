@@ -145,7 +145,7 @@ int64_t instance_bytes(int64_t n_el, int dim, int P, int precision, int M) {
   int64_t b = (kBaseSlots + M + 1) * ld * w;
   b += bs * bs * n_el * w + (int64_t)schur_numbers(dim, n_modes(dim, P)) * n_el * 4;  // blocks, FP32 factors
   b += nf * nfp * n_el * w;  // face traces of the linearisation state
-  b += std::max<int64_t>(std::max<int64_t>(66 * ntile, 4 * ntile_e), 4096) * 8;
+  b += std::max<int64_t>(std::max<int64_t>(130 * ntile, 4 * ntile_e), 4096) * 8;
   const int64_t geo = dim * dim + 1 + (dim + 1) * (dim + 1);
   b += n_el * ((dim + 1) * 4 + (dim + 1) * dim * 8 + geo * 8 + (precision == BSW_FP32 ? geo * 4 : 0));
   b += n_modes(dim, P) * n_el * w;  // bed coefficients
@@ -182,9 +182,11 @@ struct BInst {
   int it = 0, conv = 0;
   double rn = 0, rn_prev = 0, eta = 1e-3, a = 1, rnt = 0;
   // GMRES
-  std::vector<double> H, cs, sn, g, y;
+  // H: Hessenberg columns after the Givens rotations; Hu: the completed
+  // columns as formed; Hp: the latest column before its completion
+  std::vector<double> H, Hu, Hp, cs, sn, g, y;
   int j = 0, iters = 0, cycles = 0;
-  double bn = 0, beta = 0, relres = 0, rtol = 0, hn = 0;
+  double bn = 0, beta = 0, relres = 0, rtol = 0, hn = 0, gsave = 0;
   bool cyc_conv = false;
   bool own = true;  // mesh, discretisation and workspace belong to the instance
   bool finished() const { return failed || cancelled || step >= nsteps; }
@@ -452,9 +454,9 @@ struct BatchEngine {
     return BSW_OK;
   }
   // fold the partials of rows[] rows per instance into sc / sch at offset off
-  // (scl, sig: as kb_rows_final; jv: per-instance Krylov index)
+  // (scl, sig, off2: as kb_rows_final; jv: per-instance Krylov index)
   int final_rows(const std::vector<int>& L, const std::vector<int>& rows, int etile, unsigned ops, int off,
-                 int scl = 0, int sig = -1, const std::vector<int>* jv = nullptr, int gate = -1) {
+                 int scl = 0, int sig = -1, const std::vector<int>* jv = nullptr, int off2 = -1) {
     BatchSet S;
     build(S, L, K_ONE, jv);
     int mr = 0;
@@ -464,7 +466,7 @@ struct BatchEngine {
     }
     if (!mr) return BSW_OK;
     hipLaunchKernelGGL((kb_rows_final<T>), dim3((unsigned)L.size(), mr), dim3(256), 0, c->stream, d_desc, S, etile,
-                       ops, sc, sch_dev, off, scl, sig, gate);
+                       ops, sc, sch_dev, off, scl, sig, off2);
     HIPCHK(c, hipGetLastError());
     ++launches;
     return BSW_OK;
@@ -531,7 +533,7 @@ struct BatchEngine {
 
   // ------------------------------------------------------------ admission
   static int64_t part_len(int64_t len, int64_t n_el) {
-    return std::max<int64_t>(std::max<int64_t>(66 * ((len + kVT - 1) / kVT), 4 * ((n_el + 255) / 256)), 4096);
+    return std::max<int64_t>(std::max<int64_t>(130 * ((len + kVT - 1) / kVT), 4 * ((n_el + 255) / 256)), 4096);
   }
   static int64_t ws_len(int64_t len, int M) { return (int64_t)(kBaseSlots + M + 1) * round_up(len, 64); }
 
@@ -581,6 +583,8 @@ struct BatchEngine {
     I->newton_tol = std::max(o.newton_tol, floor_tol);
     I->gmres_rtol = std::max(o.gmres_rtol, sizeof(T) == 4 ? 1e-6 : 0.0);
     I->H.assign((size_t)(M + 1) * M, 0.0);
+    I->Hu.assign((size_t)(M + 1) * M, 0.0);
+    I->Hp.assign(M + 1, 0.0);
     I->cs.assign(M, 0.0);
     I->sn.assign(M, 0.0);
     I->g.assign(M + 1, 0.0);
@@ -600,21 +604,19 @@ struct BatchEngine {
   }
 
   // ------------------------------------------------------------ GMRES (lockstep, pipelined)
-  // Right-preconditioned restarted GMRES(M) with classical Gram-Schmidt and a
-  // second pass where the first cancelled more than half of the squared norm
-  // (gs_refine, decided on the device per instance), per instance:
-  // J x = rhs to ||rhs - J x|| <= rtol ||rhs|| with x = B_DW starting at 0.
-  // One Arnoldi step of every participating instance is seven launches
-  // (preconditioner, Jacobian, dots with ||w||^2, the second pass (an
-  // immediate return where it is not needed), new vector with its norm
-  // partials, and a fold kernel after each of the two Gram-Schmidt
-  // reductions; the norm partials are folded by the next step's
-  // preconditioner pass); the
-  // Hessenberg column, Givens rotations and the cycle test run on the host
-  // from the mapped scalars.  The host issues step t+1 before it reads step
-  // t (Krylov index and iteration cap known in advance), so the device never
-  // waits on the host; a step issued for an instance whose cycle turned out
-  // to end at t is discarded (it only wrote scratch vectors and V_{j+2}).
+  // Right-preconditioned restarted GMRES(M) with classical Gram-Schmidt
+  // and delayed reorthogonalisation (kb_gs_dots, kb_gs_update), per
+  // instance: J x = rhs to ||rhs - J x|| <= rtol ||rhs|| with x = B_DW
+  // starting at 0.  One Arnoldi step of every participating instance is five
+  // launches (preconditioner, Jacobian, the pass of dot products, its fold,
+  // and the pass that writes the reorthogonalised v_j and the next direction
+  // with its norm partials, which the next step's preconditioner pass
+  // folds); the Hessenberg column, Givens rotations and the cycle test run
+  // on the host from the mapped scalars.  The host issues step t+1 before it
+  // reads step t (Krylov index and iteration cap known in advance), so the
+  // device never waits on the host; a step issued for an instance whose
+  // cycle turned out to end at t is discarded (it only wrote scratch
+  // vectors, V_{j+1} and V_{j+2}, which the cycle's solution does not use).
   struct Tick {
     std::vector<int> mem, jv;
     int parity = 0;
@@ -649,7 +651,7 @@ struct BatchEngine {
     }
   }
 
-  // The norm of V_{j+1} (from the partials of kb_normalize) is folded by the
+  // The norm of V_{j+1} (from the partials of kb_gs_update) is folded by the
   // next step's preconditioner pass, which needs sigma_{j+1} first; for an
   // instance without a next step, close_norms folds it on its own.  A step's
   // completion event is recorded after those folds.
@@ -696,57 +698,84 @@ struct BatchEngine {
     if (int rc = elem_pass(1, L, jv, (int)B_W, (int)B_Z, (int)B_WK, tm ? jt1[pa] : nullptr, tm ? jt0[pa] : nullptr))
       return rc;
     --launches;  // counted with the tick's own launches below
-    // pass 1: h1 = V^T w and w . w
+    // pass 1: V^T y_j, V^T w with y_j . y_j and y_j . w (row pairs)
     nt = build(S, L, K_VEC, jv);
     int maxrows = 0;
     for (int j : tk.jv) maxrows = std::max(maxrows, j + 1);
     if (maxrows <= kRowsCached)
-      hipLaunchKernelGGL((kb_dots_cached<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
+      hipLaunchKernelGGL((kb_gs_dots_cached<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
     else
-      hipLaunchKernelGGL((kb_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
+      hipLaunchKernelGGL((kb_gs_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
     std::vector<int> rows(L.size());
-    for (size_t a = 0; a < L.size(); ++a) rows[a] = tk.jv[a] + 2;
-    if (int rc = final_rows(L, rows, 0, 0u, offA, 1, -1, jv)) return rc;
-    // pass 2 where the first left less than half of w's squared norm (the
-    // device decides per instance): h2 = V^T (w - V h1); else h2 = 0
-    if (maxrows <= kRowsCached)
-      hipLaunchKernelGGL((kb_axpy_dots_cached<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc,
-                         offA, (int)B_V0, (int)B_WK);
-    else
-      hipLaunchKernelGGL((kb_axpy_dots<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
-                         (int)B_V0, (int)B_WK);
+    for (size_t a = 0; a < L.size(); ++a) rows[a] = 2 * (tk.jv[a] + 1);
+    if (int rc = final_rows(L, rows, 0, 0u, offA, 1, -1, jv, offB)) return rc;
+    // pass 2: v_j final in place, u_{j+1} -> V_{j+1} with its norm partials
+    hipLaunchKernelGGL((kb_gs_update<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sc, sch_dev, offA, offB,
+                       kScN + 6 + pa, kScN + 8 + pa, (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
-    for (auto& r : rows) r -= 1;
-    if (int rc = final_rows(L, rows, 0, 0u, offB, 1, -1, jv, offA)) return rc;
-    // V_{j+1} = w - V (h1 + h2) and the partials of its squared norm
-    hipLaunchKernelGGL((kb_normalize<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, offA,
-                       offB, (int)B_V0, (int)B_WK);
-    HIPCHK(c, hipGetLastError());
-    launches += 5;  // prec, element pass, dots, second pass, normalize (folds count themselves)
+    launches += 4;  // prec, element pass, two Gram-Schmidt passes (folds count themselves)
     return BSW_OK;
   }
 
-  // Hessenberg column j = jv of one processed step, Givens rotations, cycle test
+  // Step j of one instance from its scalars: completes Hessenberg column
+  // j - 1 (its Arnoldi relation took u_j = ||u_j|| y_j, and y_j = V s +
+  // rho v_j), rotates it, then forms column j from this step's t and c
+  // against the completed columns (h_kj = (t_k - (Hu s)_k) / rho, the last
+  // entry ||u_{j+1}||), rotates a copy for the residual estimate and the
+  // cycle test.  Column j stays open until the next step completes it; a
+  // cycle that ends here solves with it as it stands (the true residual is
+  // formed at the cycle end).
   void arnoldi_update(BInst<T>* I, int k, int j, int pa) {
     const int offA = pa ? kScA1 : kScA, offB = pa ? kScB1 : kScB;
     double* H = I->H.data();
-    for (int i = 0; i <= j; ++i) H[(size_t)i * M + j] = rd(k, offA + i) + rd(k, offB + i);
-    I->hn = rd(k, kScN + pa);
-    H[(size_t)(j + 1) * M + j] = I->hn;
-    for (int i = 0; i < j; ++i) {
-      const double t = I->cs[i] * H[(size_t)i * M + j] + I->sn[i] * H[(size_t)(i + 1) * M + j];
-      H[(size_t)(i + 1) * M + j] = -I->sn[i] * H[(size_t)i * M + j] + I->cs[i] * H[(size_t)(i + 1) * M + j];
-      H[(size_t)i * M + j] = t;
+    double* Hu = I->Hu.data();
+    double* cs = I->cs.data();
+    double* sn = I->sn.data();
+    double* g = I->g.data();
+    const double rho = rd(k, kScN + 6 + pa), cc = rd(k, kScN + 8 + pa);
+    const double rn = rd(k, kScN + pa);  // ||u_{j+1}||
+    auto rotate = [&](double* col, int upto) {
+      for (int i = 0; i < upto; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+    };
+    auto close = [&](double* col, int jc) {  // rotation jc from col[jc], col[jc + 1]
+      const double den = std::hypot(col[jc], col[jc + 1]);
+      cs[jc] = den > 0.0 ? col[jc] / den : 1.0;
+      sn[jc] = den > 0.0 ? col[jc + 1] / den : 0.0;
+      col[jc] = den;
+      col[jc + 1] = 0.0;
+      for (int i = 0; i <= jc + 1; ++i) H[(size_t)i * M + jc] = col[i];
+      g[jc + 1] = -sn[jc] * g[jc];
+      g[jc] = cs[jc] * g[jc];
+    };
+    double col[66];
+    if (j >= 1) {
+      const double r = I->hn;  // ||u_j||
+      for (int i = 0; i < j; ++i) col[i] = I->Hp[i] + r * rd(k, offA + i);
+      col[j] = r * rho;
+      for (int i = 0; i <= j; ++i) Hu[(size_t)i * M + j - 1] = col[i];
+      rotate(col, j - 1);
+      g[j - 1] = I->gsave;
+      close(col, j - 1);
     }
-    const double den = std::hypot(H[(size_t)j * M + j], H[(size_t)(j + 1) * M + j]);
-    I->cs[j] = H[(size_t)j * M + j] / den;
-    I->sn[j] = H[(size_t)(j + 1) * M + j] / den;
-    H[(size_t)j * M + j] = den;
-    H[(size_t)(j + 1) * M + j] = 0.0;
-    I->g[j + 1] = -I->sn[j] * I->g[j];
-    I->g[j] = I->cs[j] * I->g[j];
-    I->cyc_conv = std::fabs(I->g[j + 1]) <= I->rtol * I->bn || I->hn == 0.0;
+    const double rinv = rho > 0.0 ? 1.0 / rho : 0.0;
+    for (int kk = 0; kk <= j; ++kk) {
+      double hs = 0.0;
+      for (int i = std::max(0, kk - 1); i < j; ++i) hs += Hu[(size_t)kk * M + i] * rd(k, offA + i);
+      const double tk = kk < j ? rd(k, offB + kk) : cc;
+      col[kk] = (tk - hs) * rinv;
+      I->Hp[kk] = col[kk];
+    }
+    col[j + 1] = rn;
+    rotate(col, j);
+    I->gsave = g[j];
+    close(col, j);
+    I->hn = rn;
+    I->cyc_conv = std::fabs(g[j + 1]) <= I->rtol * I->bn || rn == 0.0;
     I->iters += 1;
     I->j = j + 1;
   }

@@ -282,7 +282,19 @@ __global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict_
 // The Krylov vectors are stored unnormalised: V_true[r] = sigma_r V[r] with
 // sigma_r = sc[kScS + r], so each new vector's norm is computed exactly from
 // the vector itself and no pass only rescales.
-
+//
+// Gram-Schmidt with delayed reorthogonalisation (the DCGS2 scheme of
+// Swirydowicz, Langou, Ananthan, Yang and Thomas, 2020): at Arnoldi step j
+// the basis v_0..v_{j-1} is final, y_j = sigma_j V[j] is the new direction
+// after one projection (unit norm, not yet reorthogonalised) and w = A M^-1
+// y_j.  One pass over the basis forms s = V^T y_j, a = y_j . y_j,
+// t = V^T w and b = y_j . w; a second pass writes the reorthogonalised
+// v_j = (y_j - V s) / rho, rho = sqrt(a - s . s), and the next direction
+// u_{j+1} = (w - V t - c v_j) / rho, c = v_j . w = (b - s . t) / rho, which
+// is w's projection out of the final basis scaled as A M^-1 v_j would be.
+// The Hessenberg column of step j-1 is completed on the host from s and
+// rho (its Arnoldi relation took u_j, not v_j).  Two reads of the basis per
+// step instead of the three of classical Gram-Schmidt with a second pass.
 
 // red[u][tid] holds the 256 products of rows r0 + u (u < 8) of one tile:
 // wave w sums rows 2w and 2w + 1, each lane four consecutive products, then
@@ -302,31 +314,38 @@ __device__ __forceinline__ void fold_group(const double (&red)[8][257], int r0, 
   }
 }
 
-// per-tile partials of rows r: V_r . w (r < rows, or r < rows - 1 and the last
-// row w . w when self).  Eight rows at a time: every lane forms its two-term
-// products (sixteen independent loads in flight), the 8 x 256 products are
-// transposed through LDS and fold_group sums each row -- a fixed summation
-// order.
+// Gram-Schmidt pass 1 of step j: per-tile partials of the rows
+// 2r = V[r] . V[j] and 2r + 1 = V[r] . w for r <= j (the last pair gives
+// y_j . y_j and y_j . w once scaled), eight rows per round: products
+// transposed through LDS and summed per row by fold_group (a fixed order).
 template <class T>
-__device__ __forceinline__ void tile_dots(const InstDesc<T>& I, const T* __restrict__ V, double w0, double w1,
-                                          int64_t i0, int rows, int self, int t) {
-  __shared__ double red[8][257];
-  const int64_t i1 = i0 + 256;
-  const int nv = self ? rows - 1 : rows;  // rows against stored vectors
+__global__ void __launch_bounds__(256) kb_gs_dots(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0, int sw) {
+  const int ai = bset_find(A, blockIdx.x);
+  const InstDesc<T> I = ds[A.inst[ai]];
+  const int t = blockIdx.x - A.tile0[ai];
+  const int nv = A.jv[ai] + 1, rows = 2 * nv;
+  const T* V = bslot(I, sV0, 0);
+  const T* w = bslot(I, sw, 0);
+  const T* y = V + (int64_t)(nv - 1) * I.ld;
+  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
   const bool in0 = i0 < I.len, in1 = i1 < I.len;
+  const double y0 = in0 ? (double)y[i0] : 0.0, y1 = in1 ? (double)y[i1] : 0.0;
+  const double w0 = in0 ? (double)w[i0] : 0.0, w1 = in1 ? (double)w[i1] : 0.0;
+  __shared__ double red[8][257];
   const int tid = threadIdx.x;
   for (int r0 = 0; r0 < rows; r0 += 8) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int r = r0 + u;
-      double a = 0.0;
+    for (int u = 0; u < 8; u += 2) {
+      const int r = (r0 + u) >> 1;
+      double a = 0.0, c = 0.0;
       if (r < nv) {
         const T* v = V + (int64_t)r * I.ld;
-        a = (in0 ? (double)v[i0] * w0 : 0.0) + (in1 ? (double)v[i1] * w1 : 0.0);
-      } else if (r < rows) {
-        a = w0 * w0 + w1 * w1;
+        const double x0 = in0 ? (double)v[i0] : 0.0, x1 = in1 ? (double)v[i1] : 0.0;
+        a = x0 * y0 + x1 * y1;
+        c = x0 * w0 + x1 * w1;
       }
       red[u][tid] = a;
+      red[u + 1][tid] = c;
     }
     __syncthreads();
     fold_group(red, r0, rows, I.part, I.ntile, t);
@@ -334,45 +353,21 @@ __device__ __forceinline__ void tile_dots(const InstDesc<T>& I, const T* __restr
   }
 }
 
-// Classical Gram-Schmidt with the "refine if needed" test of Daniel, Gragg,
-// Kaufman and Stewart (1976): the second pass is taken only when the first
-// removed more than half of the squared norm, ||w - Q h||^2 = ||w||^2 -
-// ||h||^2 < ||w||^2 / 2 (Q the normalised basis).  s holds h_0..h_{rows-1}
-// (coefficients against Q) and ||w||^2; every kernel that needs the decision
-// evaluates it from the same values in the same order.
-__device__ __forceinline__ bool gs_refine(const double* __restrict__ s, int rows) {
-  double hh = 0.0;
-  for (int r = 0; r < rows; ++r) hh += s[r] * s[r];
-  const double ww = s[rows];
-  return ww - hh < 0.5 * ww;
-}
-
-// Gram-Schmidt pass 1: partials of V_r . w (r <= j) and of w . w
-template <class T>
-__global__ void __launch_bounds__(256) kb_dots(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0, int sw) {
-  const int ai = bset_find(A, blockIdx.x);
-  const InstDesc<T> I = ds[A.inst[ai]];
-  const int t = blockIdx.x - A.tile0[ai];
-  const T* w = bslot(I, sw, 0);
-  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
-  const double w0 = i0 < I.len ? (double)w[i0] : 0.0, w1 = i1 < I.len ? (double)w[i1] : 0.0;
-  tile_dots<T>(I, bslot(I, sV0, 0), w0, w1, i0, A.jv[ai] + 2, 1, t);
-}
-
-// kb_dots for instances with j + 1 <= kRowsCached: every lane first loads its
-// entries of V_0..V_j (all loads in flight at once, not eight rows per round
-// trip), then the rows are reduced as in tile_dots, in the same order
+// kb_gs_dots for instances with j + 1 <= kRowsCached: every lane first loads
+// its entries of V_0..V_j (all loads in flight at once, not four rows per
+// round trip); the rows are then reduced as in kb_gs_dots, in the same order
 constexpr int kRowsCached = 32;
 
 template <class T>
-__global__ void __launch_bounds__(256) kb_dots_cached(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0,
-                                                       int sw) {
+__global__ void __launch_bounds__(256) kb_gs_dots_cached(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0,
+                                                          int sw) {
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
   const int t = blockIdx.x - A.tile0[ai];
-  const int nv = A.jv[ai] + 1, rows = nv + 1;  // the last row is w . w
+  const int nv = A.jv[ai] + 1, rows = 2 * nv;
   const T* V = bslot(I, sV0, 0);
   const T* w = bslot(I, sw, 0);
+  const T* y = V + (int64_t)(nv - 1) * I.ld;
   const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
   const bool in0 = i0 < I.len, in1 = i1 < I.len;
   T v0[kRowsCached], v1[kRowsCached];
@@ -382,20 +377,19 @@ __global__ void __launch_bounds__(256) kb_dots_cached(const InstDesc<T>* __restr
     v0[r] = r < nv && in0 ? v[i0] : T(0);
     v1[r] = r < nv && in1 ? v[i1] : T(0);
   }
+  const double y0 = in0 ? (double)y[i0] : 0.0, y1 = in1 ? (double)y[i1] : 0.0;
   const double w0 = in0 ? (double)w[i0] : 0.0, w1 = in1 ? (double)w[i1] : 0.0;
   __shared__ double red[8][257];
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int r0 = 0; r0 < kRowsCached + 8; r0 += 8) {
+  for (int r0 = 0; r0 < 2 * kRowsCached; r0 += 8) {
     if (r0 < rows) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = r0 + u;
-        double a = 0.0;
-        if (r < kRowsCached && r < nv) a = (double)v0[r < kRowsCached ? r : 0] * w0 +
-                                           (double)v1[r < kRowsCached ? r : 0] * w1;
-        else if (r == nv) a = w0 * w0 + w1 * w1;
-        red[u][tid] = a;
+      for (int u = 0; u < 8; u += 2) {
+        const int r = (r0 + u) >> 1;
+        const double x0 = (double)v0[r], x1 = (double)v1[r];
+        red[u][tid] = x0 * y0 + x1 * y1;
+        red[u + 1][tid] = x0 * w0 + x1 * w1;
       }
       __syncthreads();
       fold_group(red, r0, rows, I.part, I.ntile, t);
@@ -404,155 +398,104 @@ __global__ void __launch_bounds__(256) kb_dots_cached(const InstDesc<T>* __restr
   }
 }
 
-// Gram-Schmidt pass 2, only where gs_refine asks for it (else the workgroup
-// returns at once and the fold writes zeros): t = w - sum_{r <= j} h_r
-// sigma_r V_r (h and ||w||^2 in row coff) in registers, w itself untouched,
-// then the partials of V_r . t (r <= j).  This variant keeps each lane's
-// entries of V_0..V_j in registers between the subtraction and the dots (one
-// read of the basis instead of two); for instances with j + 1 <= kRowsCached.
+// rho and c of step j from the folded rows s_r = sA[r] (r < j), a = sA[j],
+// t_r = sB[r], b = sB[j]; at j = 0, y_0 is the normalised residual itself
+// (rho = 1).  Every caller evaluates them in this order.
+__device__ __forceinline__ void gs_rho_c(const double* __restrict__ sA, const double* __restrict__ sB, int j,
+                                         double& rho, double& c) {
+  if (j == 0) {
+    rho = 1.0;
+    c = sB[0];
+    return;
+  }
+  double ss = 0.0, st = 0.0;
+  for (int r = 0; r < j; ++r) {
+    ss += sA[r] * sA[r];
+    st += sA[r] * sB[r];
+  }
+  const double d = sA[j] - ss;
+  rho = d > 0.0 ? sqrt(d) : 0.0;
+  c = rho > 0.0 ? (sB[j] - st) / rho : 0.0;
+}
 
+// Gram-Schmidt pass 2 of step j (coefficients in rows offA, offB of the
+// instance's scalars): V[j] <- (V[j] - sum_{r<j} (s_r sigma_r / sigma_j)
+// V[r]) / rho, so that sigma_j V[j] is v_j; V[j+1] <- (w - sum_{r<j} t_r
+// sigma_r V[r] - c v_j) / rho, unnormalised, with the partials of its
+// squared norm.  The instance's first workgroup stores rho and c (rows offR,
+// offC) in sc and its host mirror sch.
 template <class T>
-__global__ void __launch_bounds__(256) kb_axpy_dots_cached(const InstDesc<T>* __restrict__ ds, BatchSet A,
-                                                            const double* __restrict__ sc, int coff, int sV0,
-                                                            int sw) {
+__global__ void __launch_bounds__(256) kb_gs_update(const InstDesc<T>* __restrict__ ds, BatchSet A,
+                                                     double* __restrict__ sc, double* __restrict__ sch, int offA,
+                                                     int offB, int offR, int offC, int sV0, int sw) {
   const int ai = bset_find(A, blockIdx.x);
   const int slot = A.inst[ai];
   const InstDesc<T> I = ds[slot];
   const int t = blockIdx.x - A.tile0[ai];
-  const int rows = A.jv[ai] + 1;
-  const double* h = sc + (int64_t)slot * kScStride + coff;
-  if (!gs_refine(h, rows)) return;
-  const double* sg = sc + (int64_t)slot * kScStride + kScS;
-  const T* V = bslot(I, sV0, 0);
+  const int j = A.jv[ai];
+  const double* sd = sc + (int64_t)slot * kScStride;
+  const double* s = sd + offA;
+  const double* tt = sd + offB;
+  const double* sg = sd + kScS;
+  double rho, c;
+  gs_rho_c(s, tt, j, rho, c);
+  if (t == 0 && threadIdx.x == 0) {
+    double* d = sc + (int64_t)slot * kScStride;
+    double* h = sch + (int64_t)slot * kScStride;
+    d[offR] = rho;
+    h[offR] = rho;
+    d[offC] = c;
+    h[offC] = c;
+  }
+  const double rinv = rho > 0.0 ? 1.0 / rho : 0.0;
+  const double sj = sg[j];
+  const double ysc = sj > 0.0 ? 1.0 / sj : 0.0;  // ||u_j||
+  T* V = bslot(I, sV0, 0);
   const T* w = bslot(I, sw, 0);
+  T* vj = V + (int64_t)j * I.ld;
+  T* un = V + (int64_t)(j + 1) * I.ld;
   const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
   const bool in0 = i0 < I.len, in1 = i1 < I.len;
-  T v0[kRowsCached], v1[kRowsCached];
-#pragma unroll
-  for (int r = 0; r < kRowsCached; ++r) {
-    const T* v = V + (int64_t)r * I.ld;
-    v0[r] = r < rows && in0 ? v[i0] : T(0);
-    v1[r] = r < rows && in1 ? v[i1] : T(0);
-  }
+  double p0 = in0 ? (double)vj[i0] : 0.0, p1 = in1 ? (double)vj[i1] : 0.0;
   double a0 = in0 ? (double)w[i0] : 0.0, a1 = in1 ? (double)w[i1] : 0.0;
+  for (int r0 = 0; r0 < j; r0 += 8) {
+    double x0[8], x1[8], cs[8], ct[8];
 #pragma unroll
-  for (int r = 0; r < kRowsCached; ++r) {
-    const double c = r < rows ? h[r] * sg[r] : 0.0;
-    a0 -= c * (double)v0[r];
-    a1 -= c * (double)v1[r];
-  }
-  const double w0 = in0 ? a0 : 0.0, w1 = in1 ? a1 : 0.0;
-  // partials of V_r . t (r < rows), as tile_dots
-  __shared__ double red[8][257];
-  const int tid = threadIdx.x;
-  const int nrow = rows;
-#pragma unroll
-  for (int r0 = 0; r0 < kRowsCached; r0 += 8) {
-    if (r0 < nrow) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = r0 + u;
-        double a = 0.0;
-        if (r < rows) a = (double)v0[r] * w0 + (double)v1[r] * w1;
-        red[u][tid] = a;
-      }
-      __syncthreads();
-      fold_group(red, r0, nrow, I.part, I.ntile, t);
-      __syncthreads();
+    for (int u = 0; u < 8; ++u) {
+      const int r = r0 + u;
+      const T* v = V + (int64_t)r * I.ld;
+      const bool ok = r < j;
+      cs[u] = ok ? s[r] * sg[r] * ysc : 0.0;
+      ct[u] = ok ? tt[r] * sg[r] : 0.0;
+      x0[u] = ok && in0 ? (double)v[i0] : 0.0;
+      x1[u] = ok && in1 ? (double)v[i1] : 0.0;
     }
-  }
-}
-
-template <class T>
-__global__ void __launch_bounds__(256) kb_axpy_dots(const InstDesc<T>* __restrict__ ds, BatchSet A,
-                                                     const double* __restrict__ sc, int coff, int sV0, int sw) {
-  const int ai = bset_find(A, blockIdx.x);
-  const int slot = A.inst[ai];
-  const InstDesc<T> I = ds[slot];
-  const int t = blockIdx.x - A.tile0[ai];
-  const int rows = A.jv[ai] + 1;
-  const double* h = sc + (int64_t)slot * kScStride + coff;
-  if (!gs_refine(h, rows)) return;
-  const double* sg = sc + (int64_t)slot * kScStride + kScS;
-  const T* V = bslot(I, sV0, 0);
-  const T* w = bslot(I, sw, 0);
-  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
-  double a0 = i0 < I.len ? (double)w[i0] : 0.0, a1 = i1 < I.len ? (double)w[i1] : 0.0;
-  {
-    const bool in0 = i0 < I.len, in1 = i1 < I.len;
-    for (int r0 = 0; r0 < rows; r0 += 8) {
-      double v0[8], v1[8], c[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = r0 + u;
-        const T* v = V + (int64_t)r * I.ld;
-        const bool ok = r < rows;
-        c[u] = ok ? h[r] * sg[r] : 0.0;
-        v0[u] = ok && in0 ? (double)v[i0] : 0.0;
-        v1[u] = ok && in1 ? (double)v[i1] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        a0 -= c[u] * v0[u];
-        a1 -= c[u] * v1[u];
-      }
-    }
-  }
-  a0 = i0 < I.len ? a0 : 0.0;
-  a1 = i1 < I.len ? a1 : 0.0;
-  tile_dots<T>(I, V, a0, a1, i0, rows, 0, t);
-}
-
-// V_{j+1} <- w - sum_{r <= j} (h1_r + h2_r) sigma_r V_r (the two Gram-Schmidt
-// passes' coefficients, rows coff and coff2; h2 = 0 where the second pass was
-// skipped), unnormalised, and the partials of its squared norm
-template <class T>
-__global__ void __launch_bounds__(256) kb_normalize(const InstDesc<T>* __restrict__ ds, BatchSet A,
-                                                     const double* __restrict__ sc, int coff, int coff2, int sV0,
-                                                     int sw) {
-  const int ai = bset_find(A, blockIdx.x);
-  const int slot = A.inst[ai];
-  const InstDesc<T> I = ds[slot];
-  const int t = blockIdx.x - A.tile0[ai];
-  const int rows = A.jv[ai] + 1;
-  const double* h = sc + (int64_t)slot * kScStride + coff;
-  const double* h2 = sc + (int64_t)slot * kScStride + coff2;
-  const double* sg = sc + (int64_t)slot * kScStride + kScS;
-  const T* V = bslot(I, sV0, 0);
-  const T* w = bslot(I, sw, 0);
-  T* y = bslot(I, sV0, 0) + (int64_t)rows * I.ld;
-  const int64_t i0 = (int64_t)t * kVT + threadIdx.x, i1 = i0 + 256;
-  double a0 = i0 < I.len ? (double)w[i0] : 0.0, a1 = i1 < I.len ? (double)w[i1] : 0.0;
-  {
-    const bool in0 = i0 < I.len, in1 = i1 < I.len;
-    for (int r0 = 0; r0 < rows; r0 += 8) {
-      double v0[8], v1[8], c[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = r0 + u;
-        const T* v = V + (int64_t)r * I.ld;
-        const bool ok = r < rows;
-        c[u] = ok ? (h[r] + h2[r]) * sg[r] : 0.0;
-        v0[u] = ok && in0 ? (double)v[i0] : 0.0;
-        v1[u] = ok && in1 ? (double)v[i1] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        a0 -= c[u] * v0[u];
-        a1 -= c[u] * v1[u];
-      }
+    for (int u = 0; u < 8; ++u) {
+      p0 -= cs[u] * x0[u];
+      p1 -= cs[u] * x1[u];
+      a0 -= ct[u] * x0[u];
+      a1 -= ct[u] * x1[u];
     }
   }
   double q = 0.0;
-  if (i0 < I.len) { const T u = (T)a0; y[i0] = u; q += (double)u * (double)u; }
-  if (i1 < I.len) { const T u = (T)a1; y[i1] = u; q += (double)u * (double)u; }
+  if (j == 0) {
+    // v_0 is final as stored
+    if (in0) a0 -= c * sj * p0;
+    if (in1) a1 -= c * sj * p1;
+  } else {
+    if (in0) { const T v = (T)(p0 * rinv); vj[i0] = v; a0 -= c * sj * (double)v; }
+    if (in1) { const T v = (T)(p1 * rinv); vj[i1] = v; a1 -= c * sj * (double)v; }
+  }
+  if (in0) { const T u = (T)(a0 * rinv); un[i0] = u; q += (double)u * (double)u; }
+  if (in1) { const T u = (T)(a1 * rinv); un[i1] = u; q += (double)u * (double)u; }
   const double x = bred(q, 0);
   if (threadIdx.x == 0) I.part[t] = x;
 }
 
 // z = sigma_j M^{-1} V_j (the preconditioner on the stored Krylov vector j)
 // Where A.rows[ai] is set, V_j was written by the previous step's
-// kb_normalize and its squared-norm partials are still in I.part: every
+// kb_gs_update and its squared-norm partials are still in I.part: every
 // workgroup folds them (the fold of kb_rows_final, same order) into
 // sigma_j = 1 / ||V_j||, after the loads of its first phase have gone out,
 // and the instance's first workgroup stores sigma_j and the norm (row offN)
@@ -616,13 +559,13 @@ __global__ void __launch_bounds__(256) kb_vred(const InstDesc<T>* __restrict__ d
 // in a fixed order; op of row r is bits 2r..2r+1 of ops (0 sum, 1 max, 2 min)
 // scl: rows r <= j are multiplied by sigma_r (dots against stored Krylov
 // vectors); sig >= 0: row 0 is a sum of squares, its square root is written
-// and sigma_{j + sig} = 1 / root (0 for a zero vector); gate >= 0: rows of a
-// second Gram-Schmidt pass, zero where gs_refine on the first pass's row (at
-// gate) says the pass was skipped
+// and sigma_{j + sig} = 1 / root (0 for a zero vector); off2 >= 0: the row
+// pairs of kb_gs_dots, row 2r scaled by sigma_r sigma_j to off + r, row
+// 2r + 1 by sigma_r to off2 + r
 template <class T>
 __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restrict__ ds, BatchSet A, int etile,
                                                       unsigned ops, double* sc, double* sch, int off, int scl,
-                                                      int sig, int gate) {
+                                                      int sig, int off2) {
   const int ai = blockIdx.x;
   const int slot = A.inst[ai];
   const InstDesc<T> I = ds[slot];
@@ -630,12 +573,24 @@ __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restri
   if (r >= A.rows[ai]) return;
   const int op = r < 16 ? (int)((ops >> (2 * r)) & 3u) : 0;
   const int nt = etile ? I.ntile_e : I.ntile;
-  const bool skipped = gate >= 0 && !gs_refine(sc + (int64_t)slot * kScStride + gate, A.jv[ai] + 1);
-  double x = fold_partials(I.part + (int64_t)r * nt, skipped ? 0 : nt, op);
+  double x = fold_partials(I.part + (int64_t)r * nt, nt, op);
   if (threadIdx.x == 0) {
     double* s = sc + (int64_t)slot * kScStride;
     double* sh = sch + (int64_t)slot * kScStride;
     const int j = A.jv[ai];
+    if (off2 >= 0) {
+      const int q = r >> 1;
+      x *= s[kScS + q];
+      if (r & 1) {
+        s[off2 + q] = x;
+        sh[off2 + q] = x;
+      } else {
+        x *= s[kScS + j];
+        s[off + q] = x;
+        sh[off + q] = x;
+      }
+      return;
+    }
     if (sig >= 0) {
       x = sqrt(x);
       const double inv = x > 0.0 ? 1.0 / x : 0.0;
