@@ -24,10 +24,11 @@ constexpr int kMaxBatch = 128;  // instances per batch
 constexpr int kVT = 512;        // reals per vector tile (256 lanes x 2)
 // FP64 scalars per instance (device array and a host-mapped mirror):
 // Gram-Schmidt coefficient rows of even and odd Arnoldi steps, the scales of
-// the stored Krylov vectors, the Krylov combination weights and norms.
-constexpr int kScStride = 448;
+// the stored Krylov vectors, the Krylov combination weights and norms, and
+// the second Gram-Schmidt pass's weights of the stored vectors.
+constexpr int kScStride = 592;
 constexpr int kScA = 0, kScB = 72, kScA1 = 144, kScB1 = 216;
-constexpr int kScS = 288, kScY = 360, kScN = 432;
+constexpr int kScS = 288, kScY = 360, kScN = 432, kScC = 448, kScD = 520;
 constexpr int kSlotJ = 1 << 16;  // slot flag: add the instance's Krylov index
 
 struct BatchSet {
@@ -419,21 +420,23 @@ __device__ __forceinline__ void gs_rho_c(const double* __restrict__ sA, const do
 }
 
 // Gram-Schmidt pass 2 of step j (coefficients in rows offA, offB of the
-// instance's scalars): V[j] <- (V[j] - sum_{r<j} (s_r sigma_r / sigma_j)
-// V[r]) / rho, so that sigma_j V[j] is v_j; V[j+1] <- (w - sum_{r<j} t_r
-// sigma_r V[r] - c v_j) / rho, unnormalised, with the partials of its
-// squared norm.  The instance's first workgroup stores rho and c (rows offR,
-// offC) in sc and its host mirror sch.
-template <class T>
+// instance's scalars, the weights of the V[r] at kScC, kScD): V[j] <- (V[j]
+// - sum_{r<j} (s_r sigma_r / sigma_j) V[r]) / rho, so that sigma_j V[j] is
+// v_j; V[j+1] <- (w - sum_{r<j} t_r sigma_r V[r] - c v_j) / rho,
+// unnormalised, with the partials of its squared norm.  The instance's first workgroup stores rho and c (rows offR,
+// offC) in sc and its host mirror sch.  CACHED (j + 1 <= kRowsCached): every
+// lane loads its entries of V_0..V_{j-1} at once before the sums; otherwise
+// eight rows per round.  Both forms sum in the same order.
+template <class T, bool CACHED>
 __global__ void __launch_bounds__(256) kb_gs_update(const InstDesc<T>* __restrict__ ds, BatchSet A,
                                                      double* __restrict__ sc, double* __restrict__ sch, int offA,
                                                      int offB, int offR, int offC, int sV0, int sw) {
   const int ai = bset_find(A, blockIdx.x);
-  const int slot = A.inst[ai];
+  const int slot = __builtin_amdgcn_readfirstlane(A.inst[ai]);
   const InstDesc<T> I = ds[slot];
   const int t = blockIdx.x - A.tile0[ai];
-  const int j = A.jv[ai];
-  const double* sd = sc + (int64_t)slot * kScStride;
+  const int j = __builtin_amdgcn_readfirstlane(A.jv[ai]);
+  const double* sd = wave_uniform(sc + (int64_t)slot * kScStride);
   const double* s = sd + offA;
   const double* tt = sd + offB;
   const double* sg = sd + kScS;
@@ -449,7 +452,8 @@ __global__ void __launch_bounds__(256) kb_gs_update(const InstDesc<T>* __restric
   }
   const double rinv = rho > 0.0 ? 1.0 / rho : 0.0;
   const double sj = sg[j];
-  const double ysc = sj > 0.0 ? 1.0 / sj : 0.0;  // ||u_j||
+  const double* ws = sd + kScC;  // s_r sigma_r / sigma_j
+  const double* wt = sd + kScD;  // t_r sigma_r
   T* V = bslot(I, sV0, 0);
   const T* w = bslot(I, sw, 0);
   T* vj = V + (int64_t)j * I.ld;
@@ -458,24 +462,43 @@ __global__ void __launch_bounds__(256) kb_gs_update(const InstDesc<T>* __restric
   const bool in0 = i0 < I.len, in1 = i1 < I.len;
   double p0 = in0 ? (double)vj[i0] : 0.0, p1 = in1 ? (double)vj[i1] : 0.0;
   double a0 = in0 ? (double)w[i0] : 0.0, a1 = in1 ? (double)w[i1] : 0.0;
-  for (int r0 = 0; r0 < j; r0 += 8) {
-    double x0[8], x1[8], cs[8], ct[8];
+  if constexpr (CACHED) {
+    T x0[kRowsCached], x1[kRowsCached];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int r = r0 + u;
+    for (int r = 0; r < kRowsCached; ++r) {
       const T* v = V + (int64_t)r * I.ld;
-      const bool ok = r < j;
-      cs[u] = ok ? s[r] * sg[r] * ysc : 0.0;
-      ct[u] = ok ? tt[r] * sg[r] : 0.0;
-      x0[u] = ok && in0 ? (double)v[i0] : 0.0;
-      x1[u] = ok && in1 ? (double)v[i1] : 0.0;
+      x0[r] = r < j && in0 ? v[i0] : T(0);
+      x1[r] = r < j && in1 ? v[i1] : T(0);
     }
+    // (the weights past j are zero, as are those entries)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      p0 -= cs[u] * x0[u];
-      p1 -= cs[u] * x1[u];
-      a0 -= ct[u] * x0[u];
-      a1 -= ct[u] * x1[u];
+    for (int r = 0; r < kRowsCached; ++r) {
+      const double cs = ws[r], ct = wt[r];
+      p0 -= cs * (double)x0[r];
+      p1 -= cs * (double)x1[r];
+      a0 -= ct * (double)x0[r];
+      a1 -= ct * (double)x1[r];
+    }
+  } else {
+    for (int r0 = 0; r0 < j; r0 += 8) {
+      double x0[8], x1[8], cs[8], ct[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = r0 + u;
+        const T* v = V + (int64_t)r * I.ld;
+        const bool ok = r < j;
+        cs[u] = ok ? ws[r] : 0.0;
+        ct[u] = ok ? wt[r] : 0.0;
+        x0[u] = ok && in0 ? (double)v[i0] : 0.0;
+        x1[u] = ok && in1 ? (double)v[i1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        p0 -= cs[u] * x0[u];
+        p1 -= cs[u] * x1[u];
+        a0 -= ct[u] * x0[u];
+        a1 -= ct[u] * x1[u];
+      }
     }
   }
   double q = 0.0;
@@ -561,7 +584,9 @@ __global__ void __launch_bounds__(256) kb_vred(const InstDesc<T>* __restrict__ d
 // vectors); sig >= 0: row 0 is a sum of squares, its square root is written
 // and sigma_{j + sig} = 1 / root (0 for a zero vector); off2 >= 0: the row
 // pairs of kb_gs_dots, row 2r scaled by sigma_r sigma_j to off + r, row
-// 2r + 1 by sigma_r to off2 + r
+// 2r + 1 by sigma_r to off2 + r, and for r < j the weights kb_gs_update
+// gives the stored V[r] (device only): s_r sigma_r / sigma_j at kScC + r,
+// t_r sigma_r at kScD + r, zero from r = j to kRowsCached - 1
 template <class T>
 __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restrict__ ds, BatchSet A, int etile,
                                                       unsigned ops, double* sc, double* sch, int off, int scl,
@@ -580,14 +605,20 @@ __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restri
     const int j = A.jv[ai];
     if (off2 >= 0) {
       const int q = r >> 1;
-      x *= s[kScS + q];
+      const double sq = s[kScS + q];
+      x *= sq;
       if (r & 1) {
         s[off2 + q] = x;
         sh[off2 + q] = x;
+        if (q < j) s[kScD + q] = x * sq;
       } else {
-        x *= s[kScS + j];
+        const double sj = s[kScS + j];
+        x *= sj;
         s[off + q] = x;
         sh[off + q] = x;
+        if (q < j) s[kScC + q] = sj > 0.0 ? x * sq * (1.0 / sj) : 0.0;
+        if (q == j)  // weights of the rows past j are zero
+          for (int u = j; u < kRowsCached; ++u) s[kScC + u] = s[kScD + u] = 0.0;
       }
       return;
     }
