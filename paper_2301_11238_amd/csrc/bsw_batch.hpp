@@ -79,8 +79,10 @@ struct TileTuner {
       Pending& q = pend[k];
       if (hipEventQuery(q.b) != hipSuccess) { ++k; continue; }
       float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
-        Entry& E = tab[q.key];
+      // (samples still in flight when the choice was made are dropped, so the
+      // table keeps the times the choice was made from)
+      Entry& E = tab[q.key];
+      if (E.choice < 0 && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
         if (E.n[q.v] == 0 || ms < E.best_ms[q.v]) E.best_ms[q.v] = ms;
         ++E.n[q.v];
         bool all = true;
