@@ -161,13 +161,14 @@ __global__ void __launch_bounds__(256) kb_jac_columns(const InstDesc<T>* __restr
   jac_columns_elem<D, P, T>(bslot(I, sW, 0), I.trL, I.blk_raw, I.m, I.p, blockIdx.x - A.tile0[ai]);
 }
 
-// diagonal blocks of triangles, one element per workgroup (k_jac_blocks_tri)
+// the parts of the diagonal blocks of triangles the block-Jacobi factors
+// read, one element per workgroup (k_jac_blocks_tri)
 template <int P, class T>
 __global__ void __launch_bounds__(256) kb_jac_blocks_tri(const InstDesc<T>* __restrict__ ds, BatchSet A, int sW) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int ai = bset_find(A, b);
   const InstDesc<T> I = ds[A.inst[ai]];
-  jac_blocks_tri<P, T>(bslot(I, sW, 0), I.trL, I.blk_raw, I.m, I.p, b - A.tile0[ai]);
+  jac_blocks_tri<P, T, false>(bslot(I, sW, 0), I.trL, I.blk_raw, I.m, I.p, b - A.tile0[ai]);
 }
 
 // a pointer the whole wave holds, moved to scalar registers (so that the

@@ -449,6 +449,16 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
 // every point's tangent along that column (70 evaluations of the stress
 // tangent per point at P3), the pointwise work falls by N_p and the
 // contraction is a product with the basis tables.
+//
+// FULL = false assembles only what the block-Jacobi factors read: the
+// depth-velocity block A_VV, the velocity rows' stress columns A_UE, the
+// stress rows' velocity columns A_EU, and the diagonal of A_EE.  The stress
+// equations' integrands do not involve E (their tangents along a stress
+// direction are exact zeros, boundaries included), so A_EE is the mass
+// term alone, |J| on the diagonal (1 on unused modes), and is written
+// directly; A_hE and A_Eh vanish.  25 N_p (row, column field) items instead
+// of 7 N_p * 7: one round of 256 lanes at P3, and the same values where
+// both write.
 template <int P>
 struct JB2 {
   using S = Shape<2, P>;
@@ -459,7 +469,7 @@ struct JB2 {
   static constexpr int NT = 256;
 };
 
-template <int P, class T>
+template <int P, class T, bool FULL>
 __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T* __restrict__ trW,
                                                T* __restrict__ blocks, const MeshView<T>& m, const DevParams<T>& p,
                                                int e) {
@@ -549,8 +559,22 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
   __syncthreads();
   // ---------------- phase B: rows (f, i) of column field g
   T* blk = blocks + (size_t)e * S::BS * S::BS;
-  for (int b = t; b < J::NBI; b += J::NT) {
-    const int row = b / S::NF, g = b % S::NF;
+  constexpr int NP = S::NP;
+  for (int b = t; b < (FULL ? J::NBI : 25 * NP); b += J::NT) {
+    int row, g;
+    if constexpr (FULL) {
+      row = b / S::NF;
+      g = b % S::NF;
+    } else if (b < 9 * NP) {  // A_VV
+      row = b / 3;
+      g = b % 3;
+    } else if (b < 17 * NP) {  // A_UE
+      row = NP + (b - 9 * NP) / 4;
+      g = 3 + (b - 9 * NP) % 4;
+    } else {  // A_EU
+      row = 3 * NP + (b - 17 * NP) / 2;
+      g = 1 + (b - 17 * NP) % 2;
+    }
     const int f = row / S::NP, i = row % S::NP;
     T out[S::NP];
     if (row_unused<2, T>(m, f, i)) {
@@ -606,12 +630,19 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
 #pragma unroll
     for (int j = 0; j < S::NP; ++j) dst[j] = out[j];
   }
+  if constexpr (!FULL) {
+    // the diagonal of A_EE
+    for (int k = t; k < 4 * NP; k += J::NT) {
+      const int f = 3 + k / NP, i = k % NP, row = f * NP + i;
+      blk[(size_t)row * S::BS + row] = row_unused<2, T>(m, f, i) ? T(1) : geo.detJ;
+    }
+  }
 }
 
-template <int P, class T>
+template <int P, class T, bool FULL>
 __global__ void __launch_bounds__(256) k_jac_blocks_tri(const T* __restrict__ W, const T* __restrict__ trW,
                                                          T* __restrict__ blocks, MeshView<T> m, DevParams<T> p) {
-  jac_blocks_tri<P, T>(W, trW, blocks, m, p, xcd_tile(blockIdx.x, gridDim.x));
+  jac_blocks_tri<P, T, FULL>(W, trW, blocks, m, p, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Element-pass tile shapes (the autotuner's variants v = 0, 1, 2).  On

@@ -586,9 +586,11 @@ struct LinearizeLaunch {
     hipLaunchKernelGGL((k_trace<D, P, T>), grid1((int64_t)S::NF * S::NFC * m.n_el), dim3(256), 0, c->stream,
                        (const T*)d->lin_W, (T*)d->trL, m.n_el);
     const auto prm = devparams<T>(d->lin_prm, d->lin_dt, (const T*)d->dirtab);
+    // triangles: only the parts the factors read (bsw_jacobian_blocks
+    // assembles whole blocks when asked)
     if constexpr (D == 2)
-      hipLaunchKernelGGL((k_jac_blocks_tri<P, T>), dim3(m.n_el), dim3(JB2<P>::NT), 0, c->stream, (const T*)d->lin_W,
-                         (const T*)d->trL, (T*)d->blocks_raw, m, prm);
+      hipLaunchKernelGGL((k_jac_blocks_tri<P, T, false>), dim3(m.n_el), dim3(JB2<P>::NT), 0, c->stream,
+                         (const T*)d->lin_W, (const T*)d->trL, (T*)d->blocks_raw, m, prm);
     else
       hipLaunchKernelGGL((k_jac_columns<D, P, T>), dim3(cols_tiles_for(S::BS, m.n_el)), dim3(256), 0, c->stream,
                          (const T*)d->lin_W, (const T*)d->trL, (T*)d->blocks_raw, m, prm);
@@ -596,6 +598,28 @@ struct LinearizeLaunch {
     hipLaunchKernelGGL((k_schur_build<D, P, T>), dim3((unsigned)((m.n_el + kSchurEPB - 1) / kSchurEPB)), dim3(256), 0,
                        c->stream, (const T*)d->blocks_raw, (float*)d->blocks, m.n_el);
     HIPCHK(c, hipGetLastError());
+    return BSW_OK;
+  }
+};
+
+// whole diagonal blocks of triangles from the linearisation state (the
+// linearisation itself assembles only the parts its factors read)
+struct BlocksLaunch {
+  bsw_disc d;
+  template <int D, int P, class T>
+  int operator()() {
+    if constexpr (D == 2) {
+      using S = Shape<D, P>;
+      auto m = view<T>(d);
+      bsw_ctx c = d->mesh->ctx;
+      if (int rc = sync_dirtab<T>(d, d->lin_prm)) return rc;
+      hipLaunchKernelGGL((k_trace<D, P, T>), grid1((int64_t)S::NF * S::NFC * m.n_el), dim3(256), 0, c->stream,
+                         (const T*)d->lin_W, (T*)d->trL, m.n_el);
+      const auto prm = devparams<T>(d->lin_prm, d->lin_dt, (const T*)d->dirtab);
+      hipLaunchKernelGGL((k_jac_blocks_tri<P, T, true>), dim3(m.n_el), dim3(JB2<P>::NT), 0, c->stream,
+                         (const T*)d->lin_W, (const T*)d->trL, (T*)d->blocks_raw, m, prm);
+      HIPCHK(c, hipGetLastError());
+    }
     return BSW_OK;
   }
 };
@@ -1096,6 +1120,8 @@ int bsw_jacobian_blocks(bsw_disc d, void* blocks) {
   if (!d || !blocks) return fail(d ? d->mesh->ctx : nullptr, BSW_E_ARG, "null argument");
   if (!d->lin_W) return fail(d->mesh->ctx, BSW_E_STATE, "jacobian_blocks before jacobian_linearize");
   bsw_ctx c = d->mesh->ctx;
+  BlocksLaunch L{d};
+  if (int rc = dispatch(d, L)) return rc;
   const size_t bytes = (size_t)d->bs * d->bs * d->mesh->n_el * d->wsize;
   HIPCHK(c, hipMemcpyAsync(blocks, d->blocks_raw, bytes, hipMemcpyDeviceToDevice, c->stream));
   return BSW_OK;
