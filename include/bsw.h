@@ -257,8 +257,11 @@ int bsw_operator_apply(bsw_disc disc, const bsw_params* prm, double dt, const vo
  * diagonal blocks dR_e/dW_e of Eq. Newton and factors them for the
  * block-Jacobi preconditioner through the Schur complement of the stress block
  * (whose own block is the diagonal element mass matrix): the inverse of the
- * depth-velocity Schur complement (Gauss-Jordan with partial pivoting), the
- * velocity-stress couplings and the diagonal, kept in FP32. */
+ * depth-velocity Schur complement (Gauss-Jordan with partial pivoting) and
+ * the velocity rows' stress couplings, kept in FP32 (in 1-D also the stress
+ * rows' velocity couplings and the diagonal; on triangles those come from
+ * the geometry).  On triangles only the block parts the factors read are
+ * assembled here; bsw_jacobian_blocks assembles whole blocks. */
 int bsw_jacobian_linearize(bsw_disc disc, const bsw_params* prm, double dt, const void* W);
 /* y = (dR/dW)(W) x, the directional derivative including the face coupling to
  * neighbours (matrix-free): exact, HLL wave speeds included, or with them held
@@ -269,7 +272,9 @@ int bsw_jacobian_apply(bsw_disc disc, const void* x, void* y);
  * (FP32 factors, FP64 arithmetic). */
 int bsw_precond_apply(bsw_disc disc, const void* x, void* y);
 /* Writes the unfactored diagonal blocks of the last linearize to blocks
- * (device, [n_el][bs][bs] row-major, bs = n_f n_p, row/column index f*n_p+i). */
+ * (device, [n_el][bs][bs] row-major, bs = n_f n_p, row/column index f*n_p+i);
+ * on triangles they are assembled by this call from the linearisation state
+ * (which must still be as recorded), into the library's block storage. */
 int bsw_jacobian_blocks(bsw_disc disc, void* blocks);
 
 /* ---------------------------------------------------------------- stage update and reductions */
