@@ -450,15 +450,15 @@ __device__ __forceinline__ void elem2_tile(const T* __restrict__ W, const T* __r
 // tangent per point at P3), the pointwise work falls by N_p and the
 // contraction is a product with the basis tables.
 //
-// FULL = false assembles only what the block-Jacobi factors read: the
-// depth-velocity block A_VV, the velocity rows' stress columns A_UE, the
-// stress rows' velocity columns A_EU, and the diagonal of A_EE.  The stress
-// equations' integrands do not involve E (their tangents along a stress
-// direction are exact zeros, boundaries included), so A_EE is the mass
-// term alone, |J| on the diagonal (1 on unused modes), and is written
-// directly; A_hE and A_Eh vanish.  25 N_p (row, column field) items instead
-// of 7 N_p * 7: one round of 256 lanes at P3, and the same values where
-// both write.
+// FULL = false assembles only what the block-Jacobi factors read, in their
+// compact per-element layout (Schur<2, P>::CB numbers): the depth-velocity
+// block A_VV, the velocity rows' stress columns A_UE, the stress rows'
+// velocity columns A_EU, and the diagonal of A_EE.  The stress equations'
+// integrands do not involve E (their tangents along a stress direction are
+// exact zeros, boundaries included), so A_EE is the mass term alone, |J| on
+// the diagonal (1 on unused modes), and is written directly; A_hE and A_Eh
+// vanish.  25 N_p (row, column field) items instead of 7 N_p * 7: one round
+// of 256 lanes at P3, the same values as the whole blocks.
 template <int P>
 struct JB2 {
   using S = Shape<2, P>;
@@ -558,7 +558,8 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
   }
   __syncthreads();
   // ---------------- phase B: rows (f, i) of column field g
-  T* blk = blocks + (size_t)e * S::BS * S::BS;
+  using Z = Schur<2, P>;
+  T* blk = blocks + (size_t)e * (FULL ? S::BS * S::BS : Z::CB);
   constexpr int NP = S::NP;
   for (int b = t; b < (FULL ? J::NBI : 25 * NP); b += J::NT) {
     int row, g;
@@ -626,15 +627,19 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
       for (int j = 0; j < S::NP; ++j)
         if (row_unused<2, T>(m, g, j)) out[j] = T(0);
     }
-    T* dst = blk + (size_t)row * S::BS + g * S::NP;
+    T* dst;
+    if constexpr (FULL) dst = blk + (size_t)row * S::BS + g * NP;
+    else if (row < Z::NV && g < 3) dst = blk + row * Z::NV + g * NP;
+    else if (row < Z::NV) dst = blk + Z::CUE + (row - NP) * Z::NE + (g - 3) * NP;
+    else dst = blk + Z::CEU + (row - Z::NV) * Z::NU + (g - 1) * NP;
 #pragma unroll
     for (int j = 0; j < S::NP; ++j) dst[j] = out[j];
   }
   if constexpr (!FULL) {
     // the diagonal of A_EE
     for (int k = t; k < 4 * NP; k += J::NT) {
-      const int f = 3 + k / NP, i = k % NP, row = f * NP + i;
-      blk[(size_t)row * S::BS + row] = row_unused<2, T>(m, f, i) ? T(1) : geo.detJ;
+      const int f = 3 + k / NP, i = k % NP;
+      blk[Z::CDG + k] = row_unused<2, T>(m, f, i) ? T(1) : geo.detJ;
     }
   }
 }

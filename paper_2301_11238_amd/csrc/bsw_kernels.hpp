@@ -759,6 +759,11 @@ struct Schur {
   static constexpr int OH = OG + NU * NE;  // H = D^{-1} A_EU, row-major (1-D)
   static constexpr int OD = OH + NE * NU;  // d = D^{-1} (1-D)
   static constexpr int NB = GEO ? OH : OD + NE;  // numbers per element
+  // the factor build's inputs: on triangles the compact parts the
+  // linearisation assembles (per element A_VV row-major, A_UE row-major,
+  // A_EU row-major, diag A_EE; CB numbers), in 1-D whole row-major blocks
+  static constexpr int CUE = NV * NV, CEU = CUE + NU * NE, CDG = CEU + NE * NU;
+  static constexpr int CB = GEO ? CDG + NE : BS * BS;
   static_assert(NV <= 64, "the Schur complement rows must fit one wave");
 };
 // numbers per element of the stored factors (host side)
@@ -830,19 +835,22 @@ __device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float*
   __shared__ T sG[kSchurEPB][Z::NE][Z::NU];  // A_UE, transposed (velocity lane fastest)
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const T* blk = A + (size_t)(live ? e : 0) * Z::BS * Z::BS;
+  const T* blk = A + (size_t)(live ? e : 0) * Z::CB;
   float* out = F + (live ? e : 0);
   const bool own = live && lane < Z::NV;
   const bool vel = own && lane >= Z::NP;
-  const T* row = blk + (size_t)(lane < Z::NV ? lane : 0) * Z::BS;
+  // the lane's row of A_VV and, for a velocity lane, of A_UE
+  const int rl = lane < Z::NV ? lane : 0;
+  const T* row = blk + (size_t)rl * (Z::GEO ? Z::NV : Z::BS);
+  const T* urow = Z::GEO ? blk + Z::CUE + (size_t)(rl >= Z::NP ? rl - Z::NP : 0) * Z::NE : row + Z::NV;
   T a[JH];
 #pragma unroll
   for (int j = 0; j < JH; ++j) {
     const int i = lane + 64 * j < NH ? lane + 64 * j : 0;
-    a[j] = blk[(size_t)(Z::NV + i / Z::NU) * Z::BS + Z::NP + i % Z::NU];
+    a[j] = Z::GEO ? blk[Z::CEU + i] : blk[(size_t)(Z::NV + i / Z::NU) * Z::BS + Z::NP + i % Z::NU];
   }
   const int kd = lane < Z::NE ? lane : 0;
-  const T dd = blk[(size_t)(Z::NV + kd) * Z::BS + Z::NV + kd];
+  const T dd = Z::GEO ? blk[Z::CDG + kd] : blk[(size_t)(Z::NV + kd) * Z::BS + Z::NV + kd];
   T r[Z::NV];
 #pragma unroll
   for (int c = 0; c < Z::NV; ++c) r[c] = row[c];
@@ -871,7 +879,7 @@ __device__ __forceinline__ void schur_build_elem(const T* __restrict__ A, float*
   for (int k0 = 0; k0 < Z::NE; k0 += KC) {
     T g[KC];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) g[kk] = row[Z::NV + k0 + kk];
+    for (int kk = 0; kk < KC; ++kk) g[kk] = urow[k0 + kk];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       if (vel) {
