@@ -585,6 +585,12 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
 #pragma unroll
       for (int j = 0; j < S::NP; ++j) out[j] = T(0);
       // volume: C_fi(o_q^g) per point, then times phi_j(q)
+      // (for a gradient row (b, a): column a of the metric, selected here so
+      // that the geometry is not indexed at run time, which would put it in
+      // scratch memory)
+      const int bb = f >= 3 ? (f - 3) >> 1 : 0, aa = f >= 3 ? (f - 3) & 1 : 0;
+      const T xa0 = aa == 0 ? geo.xi[0][0] : geo.xi[0][1];
+      const T xa1 = aa == 0 ? geo.xi[1][0] : geo.xi[1][1];
 #pragma unroll 1
       for (int q = 0; q < S::NQ; ++q) {
         const T* o = sv[q][g];
@@ -593,8 +599,7 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
           c = sdphi[q][i][0] * o[2 + f] + sdphi[q][i][1] * o[5 + f];
           if (f > 0) c += sphi[q][i] * o[f - 1];
         } else {
-          const int bb = (f - 3) >> 1, aa = (f - 3) & 1;
-          c = (sdphi[q][i][0] * geo.xi[0][aa] + sdphi[q][i][1] * geo.xi[1][aa]) * o[8 + bb];
+          c = (sdphi[q][i][0] * xa0 + sdphi[q][i][1] * xa1) * o[8 + bb];
         }
 #pragma unroll
         for (int j = 0; j < S::NP; ++j) out[j] += c * tb.phi[q][j];
@@ -608,7 +613,6 @@ __device__ __forceinline__ void jac_blocks_tri(const T* __restrict__ W, const T*
         if (f < 3) {
           c = o[f];
         } else {
-          const int bb = (f - 3) >> 1, aa = (f - 3) & 1;
           c = o[3 + bb] * snv[fc][aa];
         }
         c *= sfphi[fc][rr][i];
