@@ -607,7 +607,7 @@ def main():
     bs = disc.nf * disc.np
     nv, nu, ne = 3 * disc.np, 2 * disc.np, 4 * disc.np
     nb_schur = nv * nv + nu * ne  # block-Jacobi factors per triangle: S^-1 and A_UE (FP32)
-    nb_read = nv * nv + 2 * nu * ne + ne  # the block entries the factor build reads
+    nb_read = nv * nv + 2 * nu * ne + ne  # the block entries the factors use (A_VV, A_UE, A_EU, diag A_EE)
 
     def single_set_kernels(Wk):
         b = disc.step_begin(cp, dt, Wk)
@@ -623,9 +623,9 @@ def main():
             "jacobian_apply": dict(seconds=t_jac, bytes=jac_bytes),
             # the FP32 factors (S^-1, A_UE), x and y
             "block_jacobi_apply": dict(seconds=t_pc, bytes=(4 * nb_schur + 2 * 8 * bs) * n_el),
-            # the FP64 diagonal blocks (written), the parts of them the factor
-            # build reads, and the FP32 factors
-            "linearisation": dict(seconds=t_lin, bytes=(8 * bs * bs + 8 * nb_read + 4 * nb_schur) * n_el),
+            # the parts of the FP64 diagonal blocks the factors use (written
+            # by the assembly, read by the factor build) and the FP32 factors
+            "linearisation": dict(seconds=t_lin, bytes=(2 * 8 * nb_read + 4 * nb_schur) * n_el),
         }
 
     if args.kernels_only:
