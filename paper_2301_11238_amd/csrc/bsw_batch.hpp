@@ -713,12 +713,8 @@ struct BatchEngine {
     for (size_t a = 0; a < L.size(); ++a) rows[a] = 2 * (tk.jv[a] + 1);
     if (int rc = final_rows(L, rows, 0, 0u, offA, 1, -1, jv, offB)) return rc;
     // pass 2: v_j final in place, u_{j+1} -> V_{j+1} with its norm partials
-    if (maxrows <= kRowsCached)
-      hipLaunchKernelGGL((kb_gs_update<T, true>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sc, sch_dev, offA,
-                         offB, kScN + 6 + pa, kScN + 8 + pa, (int)B_V0, (int)B_WK);
-    else
-      hipLaunchKernelGGL((kb_gs_update<T, false>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sc, sch_dev, offA,
-                         offB, kScN + 6 + pa, kScN + 8 + pa, (int)B_V0, (int)B_WK);
+    hipLaunchKernelGGL((kb_gs_update<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sc, sch_dev, offA, offB,
+                       kScN + 6 + pa, kScN + 8 + pa, (int)B_V0, (int)B_WK);
     HIPCHK(c, hipGetLastError());
     launches += 4;  // prec, element pass, two Gram-Schmidt passes (folds count themselves)
     return BSW_OK;

@@ -424,14 +424,16 @@ __device__ __forceinline__ void gs_rho_c(const double* __restrict__ sA, const do
 // instance's scalars, the weights of the V[r] at kScC, kScD): V[j] <- (V[j]
 // - sum_{r<j} (s_r sigma_r / sigma_j) V[r]) / rho, so that sigma_j V[j] is
 // v_j; V[j+1] <- (w - sum_{r<j} t_r sigma_r V[r] - c v_j) / rho,
-// unnormalised, with the partials of its squared norm.  The instance's first workgroup stores rho and c (rows offR,
-// offC) in sc and its host mirror sch.  CACHED (j + 1 <= kRowsCached): every
-// lane loads its entries of V_0..V_{j-1} at once before the sums; otherwise
-// eight rows per round.  Both forms sum in the same order.
-template <class T, bool CACHED>
+// unnormalised, with the partials of its squared norm.  The instance's first
+// workgroup stores rho and c (rows offR, offC) in sc and its host mirror
+// sch.  The basis is read sixteen rows per round (150 registers, three
+// waves per SIMD: 279 us per call at C3 against 296 us with every row's
+// loads issued at once at two waves per SIMD).
+template <class T>
 __global__ void __launch_bounds__(256) kb_gs_update(const InstDesc<T>* __restrict__ ds, BatchSet A,
                                                      double* __restrict__ sc, double* __restrict__ sch, int offA,
                                                      int offB, int offR, int offC, int sV0, int sw) {
+  constexpr int G = 16;
   const int ai = bset_find(A, blockIdx.x);
   const int slot = __builtin_amdgcn_readfirstlane(A.inst[ai]);
   const InstDesc<T> I = ds[slot];
@@ -463,43 +465,25 @@ __global__ void __launch_bounds__(256) kb_gs_update(const InstDesc<T>* __restric
   const bool in0 = i0 < I.len, in1 = i1 < I.len;
   double p0 = in0 ? (double)vj[i0] : 0.0, p1 = in1 ? (double)vj[i1] : 0.0;
   double a0 = in0 ? (double)w[i0] : 0.0, a1 = in1 ? (double)w[i1] : 0.0;
-  if constexpr (CACHED) {
-    T x0[kRowsCached], x1[kRowsCached];
+  for (int r0 = 0; r0 < j; r0 += G) {
+    double x0[G], x1[G], cs[G], ct[G];
 #pragma unroll
-    for (int r = 0; r < kRowsCached; ++r) {
-      const T* v = V + (int64_t)r * I.ld;
-      x0[r] = r < j && in0 ? v[i0] : T(0);
-      x1[r] = r < j && in1 ? v[i1] : T(0);
+    for (int u = 0; u < G; ++u) {
+      const int r = r0 + u;
+      const bool ok = r < j;
+      const int rr = ok ? r : 0;
+      const T* v = V + (int64_t)rr * I.ld;
+      cs[u] = ok ? ws[rr] : 0.0;
+      ct[u] = ok ? wt[rr] : 0.0;
+      x0[u] = ok && in0 ? (double)v[i0] : 0.0;
+      x1[u] = ok && in1 ? (double)v[i1] : 0.0;
     }
-    // (the weights past j are zero, as are those entries)
 #pragma unroll
-    for (int r = 0; r < kRowsCached; ++r) {
-      const double cs = ws[r], ct = wt[r];
-      p0 -= cs * (double)x0[r];
-      p1 -= cs * (double)x1[r];
-      a0 -= ct * (double)x0[r];
-      a1 -= ct * (double)x1[r];
-    }
-  } else {
-    for (int r0 = 0; r0 < j; r0 += 8) {
-      double x0[8], x1[8], cs[8], ct[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = r0 + u;
-        const T* v = V + (int64_t)r * I.ld;
-        const bool ok = r < j;
-        cs[u] = ok ? ws[r] : 0.0;
-        ct[u] = ok ? wt[r] : 0.0;
-        x0[u] = ok && in0 ? (double)v[i0] : 0.0;
-        x1[u] = ok && in1 ? (double)v[i1] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        p0 -= cs[u] * x0[u];
-        p1 -= cs[u] * x1[u];
-        a0 -= ct[u] * x0[u];
-        a1 -= ct[u] * x1[u];
-      }
+    for (int u = 0; u < G; ++u) {
+      p0 -= cs[u] * x0[u];
+      p1 -= cs[u] * x1[u];
+      a0 -= ct[u] * x0[u];
+      a1 -= ct[u] * x1[u];
     }
   }
   double q = 0.0;
@@ -587,7 +571,7 @@ __global__ void __launch_bounds__(256) kb_vred(const InstDesc<T>* __restrict__ d
 // pairs of kb_gs_dots, row 2r scaled by sigma_r sigma_j to off + r, row
 // 2r + 1 by sigma_r to off2 + r, and for r < j the weights kb_gs_update
 // gives the stored V[r] (device only): s_r sigma_r / sigma_j at kScC + r,
-// t_r sigma_r at kScD + r, zero from r = j to kRowsCached - 1
+// t_r sigma_r at kScD + r
 template <class T>
 __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restrict__ ds, BatchSet A, int etile,
                                                       unsigned ops, double* sc, double* sch, int off, int scl,
@@ -618,8 +602,6 @@ __global__ void __launch_bounds__(256) kb_rows_final(const InstDesc<T>* __restri
         s[off + q] = x;
         sh[off + q] = x;
         if (q < j) s[kScC + q] = sj > 0.0 ? x * sq * (1.0 / sj) : 0.0;
-        if (q == j)  // weights of the rows past j are zero
-          for (int u = j; u < kRowsCached; ++u) s[kScC + u] = s[kScD + u] = 0.0;
       }
       return;
     }
