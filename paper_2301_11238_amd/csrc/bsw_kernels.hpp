@@ -945,10 +945,13 @@ __global__ void __launch_bounds__(256) k_schur_build(const T* __restrict__ A, fl
 // exterior states of the boundary kinds); divided by D = |J|.  zq: z_b at the
 // volume points; zf[fc][rr][c]: z_c at the face points (unused velocity
 // modes masked out: their columns of A_EU are unit columns of the block).
-template <int P, class T>
+// emit(k, hz_k) receives row k; the loop over k is kept rolled so that only
+// one mode's reference-table entries are live (unrolled, the compiler hoists
+// all of them into scalar registers and spills those).
+template <int P, class T, class Emit>
 __device__ __forceinline__ void schur_geo_rows(const Tab<2, P, T>& tb, const MeshView<T>& m, int bc, unsigned e,
                                                int b, int a, const double (&zq)[Shape<2, P>::NQ],
-                                               const double (&zf)[3][Shape<2, P>::NFQ][2], double (&hz)[Shape<2, P>::NP]) {
+                                               const double (&zf)[3][Shape<2, P>::NFQ][2], Emit emit) {
   using S = Shape<2, P>;
   const int n = m.n_el;
   const double inv_det = 1.0 / (double)rowld(m.detJ, 0, n, e);
@@ -976,7 +979,7 @@ __device__ __forceinline__ void schur_geo_rows(const Tab<2, P, T>& tb, const Mes
 #pragma unroll
     for (int rr = 0; rr < S::NFQ; ++rr) cf[fc][rr] = sc * (double)tb.fw[rr] * (b0 * zf[fc][rr][0] + b1 * zf[fc][rr][1]);
   }
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < S::NP; ++k) {
     double v = 0.0;
 #pragma unroll
@@ -986,7 +989,7 @@ __device__ __forceinline__ void schur_geo_rows(const Tab<2, P, T>& tb, const Mes
     for (int fc = 0; fc < 3; ++fc)
 #pragma unroll
       for (int rr = 0; rr < S::NFQ; ++rr) v += (double)tb.fphi[fc][rr][k] * cf[fc][rr];
-    hz[k] = v;
+    emit(k, v);
   }
 }
 
@@ -1076,7 +1079,8 @@ __device__ __forceinline__ void schur_apply_tile(const float* __restrict__ F, co
     for (int fc = 0; fc < 3; ++fc)
 #pragma unroll
       for (int rr = 0; rr < S::NFQ; ++rr) zf[fc][rr][0] = zf[fc][rr][1] = 0.0;
-#pragma unroll
+    // (j rolled: one mode's table entries live at a time)
+#pragma unroll 1
     for (int j = 0; j < S::NP; ++j) {
       if (row_unused<D, T>(m, 1, j)) continue;  // (the two velocity fields share their order)
       const double z0 = xs[S::NP + j][lane], z1 = xs[2 * S::NP + j][lane];
@@ -1091,15 +1095,12 @@ __device__ __forceinline__ void schur_apply_tile(const float* __restrict__ F, co
           zf[fc][rr][1] += (double)tb.fphi[fc][rr][j] * z1;
         }
     }
-    double hz[S::NP];
-    schur_geo_rows<P, T>(tb, m, bc, e, b, a, zq, zf, hz);
-#pragma unroll
-    for (int k = 0; k < S::NP; ++k) {
+    schur_geo_rows<P, T>(tb, m, bc, e, b, a, zq, zf, [&](int k, double hzk) {
       const int row = fe * S::NP + k;
       double s = xs[row][lane];
-      if (!row_unused<D, T>(m, fe, k)) s -= hz[k];
+      if (!row_unused<D, T>(m, fe, k)) s -= hzk;
       rowref(y, row, n, e) = (T)(sg * s);
-    }
+    });
   } else {
     for (int k = w; k < Z::NE; k += NW) {
       double s = xs[Z::NV + k][lane];
