@@ -48,7 +48,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes of one operator apply from the rocprofv3 FETCH_SIZE and WRITE_SIZE
 # passes (KiB per dispatch), scaled by the same counters on a plain device
 # copy of known size; None until the counters are taken on the current kernel.
-TRAFFIC_BYTES = {"operator": 216987648.0}  # FETCH 70111 KiB x 2 + WRITE 71680 KiB, current kernel
+TRAFFIC_BYTES = {"operator": 216961024.0}  # FETCH 70098 KiB x 2 + WRITE 71680 KiB, current kernel
 
 
 def parse():
