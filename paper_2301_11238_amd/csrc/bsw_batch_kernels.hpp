@@ -318,8 +318,9 @@ __device__ __forceinline__ void fold_group(const double (&red)[8][257], int r0, 
 
 // Gram-Schmidt pass 1 of step j: per-tile partials of the rows
 // 2r = V[r] . V[j] and 2r + 1 = V[r] . w for r <= j (the last pair gives
-// y_j . y_j and y_j . w once scaled), eight rows per round: products
-// transposed through LDS and summed per row by fold_group (a fixed order).
+// y_j . y_j and y_j . w once scaled), eight partial rows (four basis rows)
+// per round: products transposed through LDS and summed per row by
+// fold_group (a fixed order).
 template <class T>
 __global__ void __launch_bounds__(256) kb_gs_dots(const InstDesc<T>* __restrict__ ds, BatchSet A, int sV0, int sw) {
   const int ai = bset_find(A, blockIdx.x);
