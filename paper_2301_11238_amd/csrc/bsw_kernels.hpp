@@ -1,8 +1,10 @@
 // HIP kernels of the DG operator, its tangent, the element-block Jacobian and
 // the reductions.  The state is stored SoA with the element index fastest, so
 // the coefficient loads of consecutive elements coalesce.  The reference
-// tables sit in constant memory; where the lanes of a wave read different
-// entries (different points or modes) those reads take the vector memory path.
+// tables sit in constant memory and are read through the scalar unit at
+// wave-uniform indices; where the lanes of a wave read different entries the
+// block assembly stages the tables in LDS, and the element pass reads its one
+// such table (the neighbour's face basis) through the vector memory path.
 #pragma once
 #include "bsw_device.hpp"
 
@@ -801,7 +803,8 @@ __device__ __forceinline__ double lane_value(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// The factors of element e from its diagonal block A (row-major, [e][row][col])
+// The factors of element e from its diagonal block A (the compact factor
+// inputs of Schur on triangles, [e][number]; whole row-major blocks in 1-D)
 // by one wave of a four-wave workgroup (every wave reaches the barrier; live
 // is false for a wave past the last element, whose loads then read element
 // 0's block and whose results are dropped).  D^{-1}, A_EU and the velocity
