@@ -286,7 +286,7 @@ struct BatchEngine {
     return 1;
   }
   // fills inst, tile0 and jv (the Krylov index: jv[a] if given, else the
-  // instance's current one); rows and s are zeroed
+  // instance's current one); rows are zeroed
   int build(BatchSet& S, const std::vector<int>& L, int kind, const std::vector<int>* jv = nullptr) const {
     S.n = (int)L.size();
     int tot = 0;
@@ -296,7 +296,6 @@ struct BatchEngine {
       S.tile0[a] = tot;
       S.jv[a] = (uint8_t)(jv ? (*jv)[a] : I->j);
       S.rows[a] = 0;
-      S.s[a] = 0.0;
       tot += tiles_of(I, kind);
     }
     S.tile0[L.size()] = tot;
@@ -430,11 +429,10 @@ struct BatchEngine {
   // y = a x + b z (flags as kb_lin); s[] gives the per-instance scalar
   int lin(const std::vector<int>& L, int sy, int sx, int sz, double a, double b, int flags,
           const std::vector<double>* s = nullptr) {
-    BatchSet S;
+    BatchSetS S;
     const int nt = build(S, L, K_VEC);
     if (!nt) return BSW_OK;
-    if (s)
-      for (size_t k = 0; k < L.size(); ++k) S.s[k] = (*s)[k];
+    for (size_t k = 0; k < L.size(); ++k) S.s[k] = s ? (*s)[k] : 0.0;
     hipLaunchKernelGGL((kb_lin<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, sy, sx, sz, a, b, flags);
     HIPCHK(c, hipGetLastError());
     ++launches;
@@ -442,12 +440,12 @@ struct BatchEngine {
   }
   int combine(const std::vector<int>& L, const std::vector<int>& rows, int coff, int sw, int sy, double sgn,
               int flags, const std::vector<double>* s = nullptr) {
-    BatchSet S;
+    BatchSetS S;
     const int nt = build(S, L, K_VEC);
     if (!nt) return BSW_OK;
     for (size_t k = 0; k < L.size(); ++k) {
       S.rows[k] = (uint8_t)rows[k];
-      if (s) S.s[k] = (*s)[k];
+      S.s[k] = s ? (*s)[k] : 0.0;
     }
     hipLaunchKernelGGL((kb_combine<T>), dim3(nt), dim3(256), 0, c->stream, d_desc, S, (const double*)sc, coff,
                        (int)B_V0, sw, sy, sgn, flags);

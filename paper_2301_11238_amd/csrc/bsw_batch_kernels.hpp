@@ -31,13 +31,19 @@ constexpr int kScA = 0, kScB = 72, kScA1 = 144, kScB1 = 216;
 constexpr int kScS = 288, kScY = 360, kScN = 432, kScC = 448, kScD = 520;
 constexpr int kSlotJ = 1 << 16;  // slot flag: add the instance's Krylov index
 
+// The launch set every batched kernel takes by value (about 1 KB of kernel
+// argument; a probe of six kernels per step measured about 0.6 us per KB
+// per launch).
 struct BatchSet {
   int n;                       // participating instances
   int tile0[kMaxBatch + 1];    // prefix of their tile counts
   uint16_t inst[kMaxBatch];    // engine slot
   uint8_t rows[kMaxBatch];     // per-instance row count (reductions, combinations)
   uint8_t jv[kMaxBatch];       // per-instance Krylov index
-  double s[kMaxBatch];         // per-instance scalar
+};
+// the launch set with a per-instance scalar (kb_lin, kb_combine)
+struct BatchSetS : BatchSet {
+  double s[kMaxBatch];
 };
 
 __device__ __forceinline__ int bset_find(const BatchSet& A, int b) {
@@ -227,7 +233,7 @@ __global__ void __launch_bounds__(256) kb_diag(const InstDesc<T>* __restrict__ d
 // y = a x + b z; flag 1: a = per-instance scalar, 2: b = per-instance scalar,
 // 4: y = 0, 8: no z term
 template <class T>
-__global__ void __launch_bounds__(256) kb_lin(const InstDesc<T>* __restrict__ ds, BatchSet A, int sy, int sx, int sz,
+__global__ void __launch_bounds__(256) kb_lin(const InstDesc<T>* __restrict__ ds, BatchSetS A, int sy, int sx, int sz,
                                                double ca, double cb, int flags) {
   const int ai = bset_find(A, blockIdx.x);
   const InstDesc<T> I = ds[A.inst[ai]];
@@ -251,7 +257,7 @@ __global__ void __launch_bounds__(256) kb_lin(const InstDesc<T>* __restrict__ ds
 // `coff`; flag 1: s = per-instance scalar (else 1), 2: no w term (y = sum),
 // 4: y += (instead of =) the combination, with sign sgn, 8: c_i sigma_i
 template <class T>
-__global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict__ ds, BatchSet A, const double* sc,
+__global__ void __launch_bounds__(256) kb_combine(const InstDesc<T>* __restrict__ ds, BatchSetS A, const double* sc,
                                                    int coff, int sV0, int sw, int sy, double sgn, int flags) {
   const int ai = bset_find(A, blockIdx.x);
   const int slot = A.inst[ai];
