@@ -1,7 +1,8 @@
-"""Restart lengths above the 32 Krylov rows that the register-cached
-Gram-Schmidt kernels hold: with gmres_m = 48 and 64 the first and second
-passes run their row-looping forms and the reductions span up to 65 partial
-rows.  The Newton root does not depend on the restart length, so the states
+"""Restart lengths above the 32 Krylov rows that the register-cached first
+Gram-Schmidt pass holds: with gmres_m = 48 and 64 that pass runs its
+row-looping form, the second pass reads up to 63 basis rows, and the
+reductions span up to 128 partial rows (row pairs against the new direction
+and against w).  The Newton root does not depend on the restart length, so the states
 after two implicit steps of the 8192-triangle P2 incline (the bench's
 workload) agree with the gmres_m = 30 run to well within the Newton
 tolerance, and the runs with the longer restarts take more than 32 GMRES
